@@ -1,0 +1,152 @@
+"""Oracle for exact digital circular convolution modulo a prime m.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library neither imports nor links it, and it shares no code with the product.
+
+It wraps ``oracle.c`` (plain C, exact 128-bit integer arithmetic, O(N^2)
+definitions) through ctypes.  Paper: S. S. Chandra, "Fast Digital Convolutions
+using Bit-Shifts" (arXiv:1005.1497).
+
+Parity-pinned routines (see ``tests/test_oracle_pins.py``):
+  is_prime, order, powers, inverse, ntt (forward Eq. 2 / inverse Eq. 3),
+  ntt_bins, conv_direct (Eq. 1), conv_entries, conv_via_ntt (Sec. I).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            U64, INT = ctypes.c_uint64, ctypes.c_int
+            lib.oracle_threads.restype = INT
+            lib.oracle_is_prime.argtypes = [U64]
+            lib.oracle_is_prime.restype = INT
+            lib.oracle_powers.argtypes = [U64, U64, U64, _u64p]
+            lib.oracle_order.argtypes = [U64, U64, U64]
+            lib.oracle_order.restype = U64
+            lib.oracle_inverse.argtypes = [U64, U64]
+            lib.oracle_inverse.restype = U64
+            lib.oracle_ntt.argtypes = [_u64p, _u64p, U64, U64, U64, INT]
+            lib.oracle_ntt.restype = INT
+            lib.oracle_ntt_bins.argtypes = [_u64p, U64, U64, U64, _u64p, U64, _u64p]
+            lib.oracle_ntt_bins.restype = INT
+            lib.oracle_conv_direct.argtypes = [_u64p, _u64p, _u64p, U64, U64]
+            lib.oracle_conv_entries.argtypes = [_u64p, _u64p, U64, U64, _u64p, U64, _u64p]
+            lib.oracle_conv_via_ntt.argtypes = [_u64p, _u64p, _u64p, U64, U64, U64]
+            lib.oracle_conv_via_ntt.restype = INT
+            _lib = lib
+    return _lib
+
+
+def _arr(x) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x).astype(np.uint64, copy=False))
+    return a
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_u64p)
+
+
+def threads() -> int:
+    """Number of OpenMP threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
+
+
+def is_prime(m: int) -> bool:
+    """Trial-division primality (Sec. III-A picks m prime)."""
+    return bool(_load().oracle_is_prime(int(m)))
+
+
+def powers(a: int, m: int, count: int) -> np.ndarray:
+    """Digital circle of a mod m (Eq. 5, Fig. 1): [a^0, a^1, ..., a^(count-1)] mod m."""
+    out = np.zeros(count, dtype=np.uint64)
+    _load().oracle_powers(int(a), int(m), int(count), _p(out))
+    return out
+
+
+def order(a: int, m: int, limit: int | None = None) -> int:
+    """Smallest nu >= 1 with a^nu = 1 mod m (Eq. 7); 0 if not found within limit."""
+    if limit is None:
+        limit = int(m)
+    return int(_load().oracle_order(int(a), int(m), int(limit)))
+
+
+def inverse(b: int, m: int) -> int:
+    """b^-1 mod m by the extended Euclidean algorithm (Appendix A); 0 if none."""
+    return int(_load().oracle_inverse(int(b), int(m)))
+
+
+def ntt(x, m: int, root: int, inverse: bool = False) -> np.ndarray:
+    """O(N^2) transform: Eq. 2 (forward) or Eq. 3 including N^-1 (inverse)."""
+    a = _arr(x)
+    out = np.zeros_like(a)
+    rc = _load().oracle_ntt(_p(a), _p(out), a.size, int(m), int(root), 1 if inverse else 0)
+    if rc:
+        raise ValueError("oracle_ntt failed with code %d" % rc)
+    return out
+
+
+def ntt_bins(x, m: int, root: int, bins) -> np.ndarray:
+    """Selected forward outputs X(u) of Eq. 2, each an O(N) sum."""
+    a = _arr(x)
+    b = _arr(bins)
+    out = np.zeros(b.size, dtype=np.uint64)
+    _load().oracle_ntt_bins(_p(a), a.size, int(m), int(root), _p(b), b.size, _p(out))
+    return out
+
+
+def conv_direct(f, g, m: int) -> np.ndarray:
+    """Circular convolution of Eq. 1 as the O(N^2) direct sum."""
+    fa, ga = _arr(f), _arr(g)
+    if fa.size != ga.size:
+        raise ValueError("f and g must have the same length")
+    out = np.zeros_like(fa)
+    _load().oracle_conv_direct(_p(fa), _p(ga), _p(out), fa.size, int(m))
+    return out
+
+
+def conv_entries(f, g, m: int, idx) -> np.ndarray:
+    """Selected outputs h(j) of Eq. 1, each the O(N) direct sum."""
+    fa, ga, ia = _arr(f), _arr(g), _arr(idx)
+    out = np.zeros(ia.size, dtype=np.uint64)
+    _load().oracle_conv_entries(_p(fa), _p(ga), fa.size, int(m), _p(ia), ia.size, _p(out))
+    return out
+
+
+def conv_via_ntt(f, g, m: int, root: int) -> np.ndarray:
+    """Convolution theorem (Sec. I): inverse(forward(f) * forward(g)), all O(N^2)."""
+    fa, ga = _arr(f), _arr(g)
+    out = np.zeros_like(fa)
+    rc = _load().oracle_conv_via_ntt(_p(fa), _p(ga), _p(out), fa.size, int(m), int(root))
+    if rc:
+        raise ValueError("oracle_conv_via_ntt failed with code %d" % rc)
+    return out

@@ -1,0 +1,203 @@
+/*
+ * Oracle for exact digital circular convolution modulo m.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It is deliberately plain and slow: every routine is the
+ * textbook definition written out, in exact integer arithmetic (products in
+ * unsigned 128-bit, reduced with the % operator), with no blocking, fusion or
+ * reordering beyond what the definition states.
+ *
+ * Paper: S. S. Chandra, "Fast Digital Convolutions using Bit-Shifts"
+ * (arXiv:1005.1497).  Each routine cites the passage it follows.
+ *
+ * Conventions
+ *   - All arrays are uint64_t.  Input elements may be any 64-bit value; they are
+ *     interpreted modulo m (the % in every product does this).
+ *   - Outputs are canonical residues in [0, m) (Appendix A, Sino notation).
+ *   - Routines that can fail return a nonzero int; they never abort.
+ *   - OpenMP parallelises the outer loop over output indices only; every output
+ *     is still the plain sum in index order.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef unsigned __int128 u128;
+
+/* <a*b>_m, exact (Appendix A). */
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) {
+    return (uint64_t)(((u128)a * (u128)b) % m);
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Primality by trial division with every odd d <= sqrt(m).  The method picks
+ * m prime so that every nonzero residue has a multiplicative inverse
+ * (Sec. III-A). */
+int oracle_is_prime(uint64_t m) {
+    if (m < 2) return 0;
+    if (m % 2 == 0) return m == 2;
+    for (uint64_t d = 3; d <= m / d; d += 2)
+        if (m % d == 0) return 0;
+    return 1;
+}
+
+/* The digital circle of a modulo m (Eq. 5 and Fig. 1): out[i] = a^i mod m for
+ * i < count, each term obtained from the previous one by one more factor a
+ * (for a = 2 this is doubling). */
+void oracle_powers(uint64_t a, uint64_t m, uint64_t count, uint64_t *out) {
+    uint64_t x = 1 % m;
+    for (uint64_t i = 0; i < count; ++i) {
+        out[i] = x;
+        x = mulmod(x, a, m);
+    }
+}
+
+/* Order nu of a modulo m: the smallest nu >= 1 with a^nu = 1 (mod m)
+ * (Eq. 7, Sec. II).  Walks the circle of Eq. 5 until it returns to 1.
+ * Returns 0 when the walk has not returned within `limit` steps (for example
+ * when gcd(a, m) != 1, where it never does). */
+uint64_t oracle_order(uint64_t a, uint64_t m, uint64_t limit) {
+    if (m == 1) return 1;
+    uint64_t x = 1;
+    for (uint64_t k = 1; k <= limit; ++k) {
+        x = mulmod(x, a, m);
+        if (x == 1) return k;
+    }
+    return 0;
+}
+
+/* Multiplicative inverse b^-1 modulo m by the extended Euclidean algorithm
+ * (Appendix A).  Returns 0 when gcd(b, m) != 1 (no inverse). */
+uint64_t oracle_inverse(uint64_t b, uint64_t m) {
+    __int128 r0 = (__int128)m, r1 = (__int128)(b % m);
+    __int128 s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        __int128 q = r0 / r1;
+        __int128 t = r0 - q * r1; r0 = r1; r1 = t;
+        t = s0 - q * s1; s0 = s1; s1 = t;
+    }
+    if (r0 != 1) return 0;
+    s0 %= (__int128)m;
+    if (s0 < 0) s0 += (__int128)m;
+    return (uint64_t)s0;
+}
+
+/* Transform of Eq. 2 (inverse = 0) or Eq. 3 (inverse = 1), evaluated as the
+ * O(N^2) sum, with `root` as the N-th root of unity in place of 2 (Eq. 2 is
+ * the case N = N_Max, root = 2):
+ *     forward  X(u) = < sum_t x(t) * root^(u t) >_m
+ *     inverse  x(t) = < N^-1 * sum_u X(u) * root^(-u t) >_m
+ * root^(-e) is root^(N - e mod N) (the exponent is read modulo N, Sec. I), and
+ * N^-1 comes from the extended Euclidean algorithm (Appendix A).
+ * Returns 1 if root is not an N-th root of unity, 2 if N has no inverse,
+ * 3 on allocation failure. */
+int oracle_ntt(const uint64_t *x, uint64_t *X, uint64_t N, uint64_t m,
+               uint64_t root, int inverse) {
+    if (N == 0) return 0;
+    uint64_t *P = (uint64_t *)malloc((size_t)(N + 1) * sizeof(uint64_t));
+    if (!P) return 3;
+    oracle_powers(root, m, N + 1, P);
+    if (P[N] != 1 % m) { free(P); return 1; }
+    uint64_t ninv = 1 % m;
+    if (inverse) {
+        ninv = oracle_inverse(N % m, m);
+        if (ninv == 0) { free(P); return 2; }
+    }
+    long long n = (long long)N;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long long u = 0; u < n; ++u) {
+        u128 acc = 0;
+        for (uint64_t t = 0; t < N; ++t) {
+            uint64_t e = ((uint64_t)u * t) % N;
+            if (inverse) e = (N - e) % N;
+            acc += (u128)mulmod(x[t], P[e], m);
+        }
+        uint64_t s = (uint64_t)(acc % m);
+        X[u] = inverse ? mulmod(s, ninv, m) : s;
+    }
+    free(P);
+    return 0;
+}
+
+/* Selected outputs of the forward transform of Eq. 2: out[i] = X(bins[i]).
+ * Each is the O(N) sum over t with root^(u t) built up one factor at a time.
+ * Used to check single outputs of very long transforms. */
+int oracle_ntt_bins(const uint64_t *x, uint64_t N, uint64_t m, uint64_t root,
+                    const uint64_t *bins, uint64_t nbins, uint64_t *out) {
+    long long nb = (long long)nbins;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long long i = 0; i < nb; ++i) {
+        /* z = root^u by repeated multiplication, then sum_t x(t) z^t */
+        uint64_t u = bins[i] % (N ? N : 1), z = 1 % m;
+        for (uint64_t k = 0; k < u; ++k) z = mulmod(z, root, m);
+        u128 acc = 0;
+        uint64_t zt = 1 % m;
+        for (uint64_t t = 0; t < N; ++t) {
+            acc += (u128)mulmod(x[t], zt, m);
+            zt = mulmod(zt, z, m);
+        }
+        out[i] = (uint64_t)(acc % m);
+    }
+    return 0;
+}
+
+/* Circular convolution of Eq. 1, the O(N^2) direct sum:
+ *     h(j) = < sum_{k<N} f(k) * g((j - k) mod N) >_m
+ * (the index of g is read modulo N: the sequences are periodic, Sec. I). */
+void oracle_conv_direct(const uint64_t *f, const uint64_t *g, uint64_t *h,
+                        uint64_t N, uint64_t m) {
+    long long n = (long long)N;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long long j = 0; j < n; ++j) {
+        u128 acc = 0;
+        for (uint64_t k = 0; k < N; ++k) {
+            uint64_t idx = ((uint64_t)j + N - k) % N;
+            acc += (u128)mulmod(f[k], g[idx], m);
+        }
+        h[j] = (uint64_t)(acc % m);
+    }
+}
+
+/* Selected outputs of Eq. 1: out[i] = h(idx[i]), each the O(N) direct sum. */
+void oracle_conv_entries(const uint64_t *f, const uint64_t *g, uint64_t N,
+                         uint64_t m, const uint64_t *idx, uint64_t nidx,
+                         uint64_t *out) {
+    long long ni = (long long)nidx;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long long i = 0; i < ni; ++i) {
+        uint64_t j = idx[i] % N;
+        u128 acc = 0;
+        for (uint64_t k = 0; k < N; ++k)
+            acc += (u128)mulmod(f[k], g[(j + N - k) % N], m);
+        out[i] = (uint64_t)(acc % m);
+    }
+}
+
+/* Circular convolution through the convolution theorem (Sec. I): transform f
+ * and g with Eq. 2, multiply the coefficients, invert with Eq. 3.  Every step
+ * is the O(N^2) sum of oracle_ntt.  Returns oracle_ntt's error codes. */
+int oracle_conv_via_ntt(const uint64_t *f, const uint64_t *g, uint64_t *h,
+                        uint64_t N, uint64_t m, uint64_t root) {
+    if (N == 0) return 0;
+    uint64_t *F = (uint64_t *)malloc((size_t)N * sizeof(uint64_t));
+    uint64_t *G = (uint64_t *)malloc((size_t)N * sizeof(uint64_t));
+    if (!F || !G) { free(F); free(G); return 3; }
+    int rc = oracle_ntt(f, F, N, m, root, 0);
+    if (!rc) rc = oracle_ntt(g, G, N, m, root, 0);
+    if (!rc) {
+        for (uint64_t u = 0; u < N; ++u) F[u] = mulmod(F[u], G[u], m);
+        rc = oracle_ntt(F, h, N, m, root, 1);
+    }
+    free(F); free(G);
+    return rc;
+}

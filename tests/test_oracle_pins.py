@@ -1,0 +1,298 @@
+"""Pins for the oracle, checked on the CPU against what the paper and the
+mathematics fix, never against the oracle itself.
+
+Each oracle routine is pinned by at least one check that a plausible mistake in
+it (a dropped term, a wrong sign or index, a transposed operand, a wrong
+normalisation, an overflow) would fail:
+
+  powers / order   Fig. 1 sequences and N_Max; Table 1 N_Max; Sec. II (341, nu=10);
+                   Prop. 1 (Fermat moduli); Prop. 2 proof (F_5 factors).
+  is_prime         Table 1 primes; 341 composite; F_5 = 641 * 6700417; the printed
+                   factorisations of 2^n - 1; a sieve of Eratosthenes.
+  inverse          closed form N^-1 = 2^(nu - n) for the Rader primes; b*b^-1 = 1
+                   checked with Python integers.
+  ntt (Eq. 2, 3)   closed forms: delta_0 -> all ones, ones -> N*delta_0,
+                   delta_1 -> root^u (fixes order and sign), linearity, round trip,
+                   inverse of delta_1 -> N^-1 root^-t.
+  conv_direct      numpy integer convolution folded mod N (exact small values);
+                   shift by a delta; commutativity; Python big integers for the
+                   45-bit prime.
+  conv_via_ntt     equals conv_direct (convolution theorem) for every Table 1
+                   prime and every N up to min(N_Max, 1024); independent of which
+                   primitive N-th root is used.
+  ntt_bins /       equal the matching entries of the full O(N^2) outputs.
+  conv_entries
+"""
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+TABLE1 = gold("table1_rader_primes.json")["rows"]
+
+
+def root_of_order(m, nu, N, odd=1):
+    """2^k with k = (nu / N) * odd: an element of exact order N (Python pow)."""
+    return pow(2, (nu // N) * odd, m)
+
+
+# ---------------------------------------------------------------- digital circles
+@pytest.mark.parametrize("c", gold("fig1_digital_circles.json")["circles"], ids=lambda c: c["panel"])
+def test_fig1_digital_circles(c):
+    seq = oracle.powers(c["a"], c["m"], len(c["sequence"]))
+    assert seq.tolist() == c["sequence"]
+    assert oracle.order(c["a"], c["m"]) == c["n_max"]
+
+
+@pytest.mark.parametrize("row", TABLE1, ids=lambda r: str(r["m"]))
+def test_table1_primes_and_orders(row):
+    m = row["m"]
+    assert oracle.is_prime(m)
+    assert oracle.order(2, m) == row["n_max"]
+    # m divides F_k = 2^(2^k) + 1, i.e. 2^(N_Max/2) = -1 (mod m), N_Max = 2^(k+1)
+    assert row["n_max"] == 2 ** (row["fermat_index"] + 1)
+    assert pow(2, row["n_max"] // 2, m) == m - 1
+    # Euler form of Fermat factors, k * 2^(n+2) + 1 (Sec. III-A)
+    assert (m - 1) % 2 ** (row["fermat_index"] + 2) == 0
+
+
+def test_341_poulet():
+    g = gold("carmichael_341.json")
+    assert not oracle.is_prime(g["m"])
+    assert int(np.prod(g["factors"])) == g["m"]
+    assert all(oracle.is_prime(p) for p in g["factors"])
+    assert oracle.order(2, g["m"]) == g["order_of_2"]
+    assert int(np.prod(g["mersenne_2_10_minus_1_factors"])) == 2 ** 10 - 1
+    assert pow(2, 340, 341) == 1
+
+
+def test_prop2_fermat_f5_factors():
+    g = gold("fermat_f5_factors.json")
+    p, q = g["factors"]
+    assert p * q == 2 ** 32 + 1
+    assert oracle.is_prime(p) and oracle.is_prime(q)
+    assert not oracle.is_prime(2 ** 32 + 1)
+    assert oracle.order(2, p) == g["n_max"] and oracle.order(2, q) == g["n_max"]
+
+
+@pytest.mark.parametrize("c", gold("fermat_moduli_prop1.json")["cases"], ids=lambda c: str(c["m"]))
+def test_prop1_fermat_moduli(c):
+    m = 2 ** (2 ** c["fermat_index"]) + 1
+    assert m == c["m"]
+    assert oracle.is_prime(m)
+    assert oracle.order(2, m) == c["nu"]
+
+
+def test_mersenne_factorisations():
+    for n, facs in gold("mersenne_factorisations.json")["factorisations"].items():
+        assert int(np.prod(facs)) == 2 ** int(n) - 1
+        assert all(oracle.is_prime(p) for p in facs)
+
+
+def test_is_prime_matches_sieve():
+    lim = 20000
+    sieve = np.ones(lim, dtype=bool)
+    sieve[:2] = False
+    for i in range(2, int(lim ** 0.5) + 1):
+        if sieve[i]:
+            sieve[i * i::i] = False
+    got = np.array([oracle.is_prime(i) for i in range(lim)])
+    assert np.array_equal(got, sieve)
+
+
+def test_u64_rader_prime():
+    """The 64-bit-word prime: prime, 2 of order 2^18, a factor of F_17."""
+    m = si.M_U64
+    assert m == 59251857 * 2 ** 19 + 1
+    assert oracle.is_prime(m)
+    assert oracle.order(2, m, limit=1 << 20) == si.M_U64_NMAX
+    assert pow(2, 2 ** 17, m) == m - 1
+
+
+def test_order_not_found_returns_zero():
+    # 2 is not invertible mod 16: the walk never returns to 1
+    assert oracle.order(2, 16, limit=1000) == 0
+
+
+# ---------------------------------------------------------------- inverse
+@pytest.mark.parametrize("row", TABLE1, ids=lambda r: str(r["m"]))
+def test_inverse_closed_form(row):
+    m, nu = row["m"], row["n_max"]
+    n = 0
+    while (1 << n) <= nu:
+        # N^-1 = 2^-n = 2^(nu - n) because 2^nu = 1
+        assert oracle.inverse(1 << n, m) == pow(2, nu - n, m)
+        n += 1
+    rng = random.Random(7)
+    for _ in range(200):
+        b = rng.randrange(1, m)
+        assert (oracle.inverse(b, m) * b) % m == 1
+    assert oracle.inverse(0, m) == 0
+
+
+def test_inverse_no_inverse():
+    assert oracle.inverse(11, 341) == 0
+    assert oracle.inverse(6, 9) == 0
+
+
+# ---------------------------------------------------------------- transform
+def _cases(max_n=256):
+    for row in TABLE1 + [{"m": si.M_U64, "n_max": si.M_U64_NMAX}]:
+        N = 1
+        while N <= min(row["n_max"], max_n):
+            yield row["m"], row["n_max"], N
+            N *= 2
+
+
+@pytest.mark.parametrize("m,nu,N", list(_cases()))
+def test_ntt_closed_forms(m, nu, N):
+    w = root_of_order(m, nu, N)
+    d0 = np.zeros(N, dtype=np.uint64); d0[0] = 1
+    assert oracle.ntt(d0, m, w).tolist() == [1] * N
+    ones = np.ones(N, dtype=np.uint64)
+    exp = [0] * N; exp[0] = N % m
+    assert oracle.ntt(ones, m, w).tolist() == exp
+    if N > 1:
+        d1 = np.zeros(N, dtype=np.uint64); d1[1] = 1
+        # X(u) = root^(+u): pins the order of the outputs and the sign of Eq. 2
+        assert oracle.ntt(d1, m, w).tolist() == [pow(w, u, m) for u in range(N)]
+        # inverse of delta_1: N^-1 * root^(-t) (Eq. 3)
+        ninv = pow(N, -1, m)
+        winv = pow(w, -1, m)
+        assert oracle.ntt(d1, m, w, inverse=True).tolist() == [ninv * pow(winv, t, m) % m for t in range(N)]
+    rng = np.random.default_rng(N)
+    x = rng.integers(0, m, N, dtype=np.uint64)
+    y = rng.integers(0, m, N, dtype=np.uint64)
+    X, Y = oracle.ntt(x, m, w), oracle.ntt(y, m, w)
+    s = np.array([(int(a) + int(b)) % m for a, b in zip(x, y)], dtype=np.uint64)
+    assert oracle.ntt(s, m, w).tolist() == [(int(a) + int(b)) % m for a, b in zip(X, Y)]
+    assert oracle.ntt(X, m, w, inverse=True).tolist() == x.tolist()
+
+
+def test_ntt_python_bigint_small():
+    """Eq. 2 for a 45-bit modulus, where products need 90 bits: Python integers."""
+    m, nu = si.M_U64, si.M_U64_NMAX
+    for N in (2, 8, 32):
+        w = root_of_order(m, nu, N, odd=3)
+        x = [random.Random(N).randrange(m) for _ in range(N)]
+        exp = [sum(x[t] * pow(w, u * t, m) for t in range(N)) % m for u in range(N)]
+        assert oracle.ntt(x, m, w).tolist() == exp
+
+
+def test_ntt_rejects_wrong_root():
+    with pytest.raises(ValueError):
+        oracle.ntt(np.arange(8), 13631489, 3)
+
+
+def test_ntt_bins_match_full():
+    m, nu, N = 13631489, 1 << 19, 512
+    w = root_of_order(m, nu, N, odd=5)
+    x = np.random.default_rng(3).integers(0, m, N, dtype=np.uint64)
+    full = oracle.ntt(x, m, w)
+    bins = np.array([0, 1, 2, 255, 256, 511, 77])
+    assert oracle.ntt_bins(x, m, w, bins).tolist() == full[bins].tolist()
+
+
+# ---------------------------------------------------------------- convolution
+def _circular_int(f, g):
+    """Exact integer circular convolution via numpy's linear convolution."""
+    N = len(f)
+    lin = np.convolve(np.asarray(f, dtype=np.int64), np.asarray(g, dtype=np.int64))
+    out = lin[:N].copy()
+    out[:N - 1] += lin[N:]
+    return out
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 64, 1000])
+def test_conv_direct_vs_numpy(N):
+    m = 13631489
+    rng = np.random.default_rng(N)
+    f = rng.integers(0, 60, N)
+    g = rng.integers(0, 60, N)
+    assert oracle.conv_direct(f, g, m).tolist() == (_circular_int(f, g) % m).tolist()
+
+
+def test_conv_direct_reduces_large_inputs():
+    """Inputs are residues: values >= m behave like their remainders."""
+    m, N = 641, 16
+    rng = np.random.default_rng(1)
+    f = rng.integers(0, 2 ** 63, N, dtype=np.uint64)
+    g = rng.integers(0, 2 ** 63, N, dtype=np.uint64)
+    fr = [int(v) % m for v in f]
+    gr = [int(v) % m for v in g]
+    assert oracle.conv_direct(f, g, m).tolist() == (_circular_int(fr, gr) % m).tolist()
+
+
+def test_conv_direct_shift_and_commute():
+    m, N = 13631489, 128
+    rng = np.random.default_rng(2)
+    g = rng.integers(0, m, N, dtype=np.uint64)
+    f = rng.integers(0, m, N, dtype=np.uint64)
+    for s in (0, 1, 5, 127):
+        d = np.zeros(N, dtype=np.uint64); d[s] = 1
+        assert oracle.conv_direct(d, g, m).tolist() == np.roll(g, s).tolist()
+    assert oracle.conv_direct(f, g, m).tolist() == oracle.conv_direct(g, f, m).tolist()
+
+
+def test_conv_direct_u64_bigint():
+    m = si.M_U64
+    for N in (4, 16, 64):
+        r = random.Random(N)
+        f = [r.randrange(m) for _ in range(N)]
+        g = [r.randrange(m) for _ in range(N)]
+        exp = [sum(f[k] * g[(j - k) % N] for k in range(N)) % m for j in range(N)]
+        assert oracle.conv_direct(f, g, m).tolist() == exp
+
+
+def _conv_cases():
+    for row in TABLE1:
+        N = 1
+        while N <= min(row["n_max"], 1024):
+            yield row["m"], row["n_max"], N
+            N *= 2
+
+
+@pytest.mark.parametrize("m,nu,N", list(_conv_cases()))
+def test_convolution_theorem(m, nu, N):
+    rng = np.random.default_rng(1000 + N)
+    f = rng.integers(0, m, N, dtype=np.uint64)
+    g = rng.integers(0, m, N, dtype=np.uint64)
+    direct = oracle.conv_direct(f, g, m)
+    assert oracle.conv_via_ntt(f, g, m, root_of_order(m, nu, N)).tolist() == direct.tolist()
+    if N > 2:
+        # any primitive N-th root gives the same convolution
+        assert oracle.conv_via_ntt(f, g, m, root_of_order(m, nu, N, odd=3)).tolist() == direct.tolist()
+
+
+def test_conv_entries_match_full():
+    m, N = 13631489, 300
+    rng = np.random.default_rng(9)
+    f = rng.integers(0, m, N, dtype=np.uint64)
+    g = rng.integers(0, m, N, dtype=np.uint64)
+    full = oracle.conv_direct(f, g, m)
+    idx = np.array([0, 1, 150, 299, 42])
+    assert oracle.conv_entries(f, g, m, idx).tolist() == full[idx].tolist()
+
+
+def test_worked_example_f17():
+    """m = F_2 = 17 (Prop. 1), N = 8, root 2: the integer product of the
+    polynomials 1+2x+3x^2+4x^3 and 5+6x+7x^2 reduced mod 17."""
+    f = [1, 2, 3, 4, 0, 0, 0, 0]
+    g = [5, 6, 7, 0, 0, 0, 0, 0]
+    lin = np.convolve([1, 2, 3, 4], [5, 6, 7]).tolist()
+    exp = [(lin[j] if j < len(lin) else 0) % 17 for j in range(8)]
+    assert oracle.conv_via_ntt(f, g, 17, 2).tolist() == exp
+    assert oracle.conv_direct(f, g, 17).tolist() == exp
