@@ -1,0 +1,124 @@
+/*
+ * nttmi: exact digital circular convolution modulo a prime m through a
+ * number-theoretic transform whose root of unity is a power of two, on AMD
+ * MI355X (gfx950).
+ *
+ * Method: S. S. Chandra, "Fast Digital Convolutions using Bit-Shifts"
+ * (arXiv:1005.1497).  The circular convolution of Eq. 1 is computed with the
+ * convolution theorem (Sec. I): forward transform of both sequences (Eq. 2),
+ * pointwise product modulo m, inverse transform with the factor N^-1 (Eq. 3).
+ * The root of unity of order N is a power of two 2^k modulo a Rader prime m
+ * (a prime factor of a Fermat number, Prop. 2; Table 1), so the transform
+ * coefficients are the "harmonics" 2^e mod m of the digital circle (Eq. 5).
+ *
+ * C ABI.  No C++ types and no exceptions cross this boundary.  All pointers
+ * named f, g, h, x, X are DEVICE pointers to little-endian unsigned words of
+ * elem_bits bits, owned by the caller; the library keeps none of them after
+ * a call returns.  `stream` is a hipStream_t (NULL = the null stream).
+ *
+ * Results are exact residues in canonical form [0, m) (Appendix A).  Inputs
+ * may hold any elem_bits-bit value; it is read modulo m.
+ *
+ * Every call validates its arguments on the host before any device work and
+ * returns a status; on an argument error nothing is enqueued and no memory is
+ * touched.  On success the work is enqueued on `stream` and the call returns
+ * without waiting; device faults surface at the caller's next
+ * synchronisation.  The library owns per-plan device tables (powers of the
+ * root) and workspaces in process-wide caches, created on first use and freed
+ * by ntt_release_caches().  Calls are thread-safe; calls that overlap on the
+ * same stream are ordered by the stream.
+ */
+#ifndef NTTMI_H
+#define NTTMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NTT_OK = 0,
+    NTT_E_ARG = 1,          /* null pointer, bad elem_bits, bad descriptor, partial overlap */
+    NTT_E_MODULUS = 2,      /* m not prime, order of 2 mod m not a power of two, or m too
+                               wide for elem_bits (32-bit words: m < 2^24) */
+    NTT_E_LENGTH = 3,       /* N = 2^log2n does not divide the order of 2 mod m */
+    NTT_E_ROOT = 4,         /* root is not of exact order N modulo m */
+    NTT_E_RANGE = 5,        /* an operand >= m, only with NTT_FLAG_CHECK_RANGE */
+    NTT_E_NOMEM = 6,        /* device or host allocation failed */
+    NTT_E_DEVICE = 7,       /* a HIP runtime call or kernel launch failed */
+    NTT_E_UNSUPPORTED = 8   /* a valid request this build does not implement */
+} ntt_status;
+
+/* Flags (bitwise OR). */
+#define NTT_FLAG_CHECK_RANGE   0x1u  /* reject operands >= m with NTT_E_RANGE; this
+                                        reads them back and synchronises the stream */
+#define NTT_FLAG_PER_ITEM      0x2u  /* conv_batched: one launch sequence per item
+                                        (the unfused reference form) */
+#define NTT_FLAG_PER_CLASS     0x4u  /* conv_batched: one launch per length class
+                                        instead of one persistent launch */
+
+/* Batch of independent convolutions of uneven power-of-two lengths.
+ * Item i has length N_i = 2^log2n[i] and occupies elements
+ * [offset[i], offset[i] + N_i) of each of f, g and h.  Items must not overlap
+ * one another.  Both arrays are HOST memory and are read during the call only. */
+typedef struct {
+    uint32_t        count;   /* number of items (0 is allowed: nothing to do) */
+    const uint8_t  *log2n;   /* [count] log2 of each length */
+    const uint64_t *offset;  /* [count] element offset of each item */
+} ntt_batch_desc;
+
+/* Forward transform of Eq. 2 with `root` in place of 2 (Eq. 2 is the case
+ * N = N_Max, root = 2):  X(u) = < sum_t x(t) root^(u t) >_m, u = 0..N-1, in
+ * natural order.  `batch` rows of N = 2^log2n contiguous elements each.
+ * Requirements: m prime with ord_m(2) = nu a power of two (Sec. II, Prop. 2),
+ * N | nu (Sec. I), root of exact order N (root^(N/2) = m - 1 for N >= 2,
+ * root = 1 for N = 1).  In place (x == X) is allowed. */
+ntt_status ntt_forward(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
+                       const void *x, void *X, uint32_t batch, uint32_t flags,
+                       void *stream);
+
+/* Inverse transform of Eq. 3, including the factor N^-1 (the multiplicative
+ * inverse of N modulo m, Appendix A):  x(t) = < N^-1 sum_u X(u) root^(-u t) >_m.
+ * ntt_inverse(ntt_forward(x)) = x for x in [0, m).  Same requirements and
+ * layout as ntt_forward; in place allowed. */
+ntt_status ntt_inverse(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
+                       const void *X, void *x, uint32_t batch, uint32_t flags,
+                       void *stream);
+
+/* Circular convolution of Eq. 1 of two length-N sequences:
+ *   h(j) = < sum_{k<N} f(k) g(j - k mod N) >_m
+ * computed by the convolution theorem with the given root.  h may equal f or g
+ * (in place); partial overlap is NTT_E_ARG. */
+ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
+                         const void *f, const void *g, void *h, uint32_t flags,
+                         void *stream);
+
+/* A batch of independent circular convolutions of uneven power-of-two lengths
+ * (see ntt_batch_desc), all modulo the same m.  `root` has exact order
+ * 2^root_log2order; item i uses root^(2^(root_log2order - log2n[i])), of
+ * exact order N_i, so log2n[i] <= root_log2order is required.  The usual choice
+ * is root = 2 and root_log2order = log2(ord_m(2)).  Default form: one fused
+ * forward/pointwise/inverse launch for the whole batch. */
+ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
+                        const ntt_batch_desc *d, const void *f, const void *g, void *h,
+                        uint32_t flags, void *stream);
+
+/* The default root for length 2^log2n: 2^(nu / N), nu = ord_m(2) (the harmonic
+ * of the digital circle of Eq. 5 that has exact order N).  Writes it to *root. */
+ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t *root);
+
+/* log2 of ord_m(2) for a valid modulus (Prop. 2), written to *log2_nu. */
+ntt_status ntt_modulus_order(uint64_t m, uint32_t *log2_nu);
+
+/* Static description of a status code. */
+const char *ntt_status_string(ntt_status s);
+
+/* Frees every cached plan and workspace (waits for the device first). */
+void ntt_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTTMI_H */

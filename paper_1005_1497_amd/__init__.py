@@ -1,0 +1,221 @@
+"""nttmi: exact digital circular convolution modulo a prime on AMD MI355X.
+
+Thin ctypes binding over the C ABI declared in ``include/nttmi.h``
+(``libnttmi.so``, built in-tree by ``paper_1005_1497_amd/build.py``).  This
+module only marshals arguments: every step of every transform and convolution
+runs in the library's HIP kernels.  PyTorch supplies device memory and streams.
+
+Method: S. S. Chandra, "Fast Digital Convolutions using Bit-Shifts"
+(arXiv:1005.1497): circular convolution (Eq. 1) by the convolution theorem with
+a number-theoretic transform (Eqs. 2, 3) whose root of unity is a power of two
+modulo a Rader prime (Prop. 2, Table 1).
+
+Tensors are CUDA (HIP) tensors of 32-bit words (torch.int32 or torch.uint32,
+values read as unsigned); results are canonical residues in [0, m).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched",
+    "default_root", "modulus_order", "release_caches", "status_string",
+    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "STATUS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnttmi.so")
+
+STATUS = {
+    0: "NTT_OK", 1: "NTT_E_ARG", 2: "NTT_E_MODULUS", 3: "NTT_E_LENGTH", 4: "NTT_E_ROOT",
+    5: "NTT_E_RANGE", 6: "NTT_E_NOMEM", 7: "NTT_E_DEVICE", 8: "NTT_E_UNSUPPORTED",
+}
+FLAG_CHECK_RANGE = 0x1
+FLAG_PER_ITEM = 0x2
+FLAG_PER_CLASS = 0x4
+
+EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "ntt_default_root",
+           "ntt_modulus_order", "ntt_status_string", "ntt_release_caches")
+
+
+class NttError(RuntimeError):
+    """A library call returned a status other than NTT_OK."""
+
+    def __init__(self, status: int, where: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__("%s: %s (%s)" % (where, self.name, status_string(status)))
+
+
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint32),
+                ("log2n", ctypes.POINTER(ctypes.c_uint8)),
+                ("offset", ctypes.POINTER(ctypes.c_uint64))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libnttmi.so is not built: run `python paper_1005_1497_amd/build.py` "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    U64, U32, I32, VP = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
+    for name in ("ntt_forward", "ntt_inverse"):
+        fn = getattr(L, name)
+        fn.argtypes = [U64, U32, U64, U32, VP, VP, U32, U32, VP]
+        fn.restype = I32
+    L.conv_circular.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, VP]
+    L.conv_circular.restype = I32
+    L.conv_batched.argtypes = [U64, U64, U32, U32, ctypes.POINTER(_BatchDesc), VP, VP, VP, U32, VP]
+    L.conv_batched.restype = I32
+    L.ntt_default_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
+    L.ntt_default_root.restype = I32
+    L.ntt_modulus_order.argtypes = [U64, ctypes.POINTER(U32)]
+    L.ntt_modulus_order.restype = I32
+    L.ntt_status_string.argtypes = [I32]
+    L.ntt_status_string.restype = ctypes.c_char_p
+    L.ntt_release_caches.argtypes = []
+    L.ntt_release_caches.restype = None
+    return L
+
+
+lib = _load()
+
+
+def status_string(status: int) -> str:
+    return lib.ntt_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise NttError(status, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+_WORD = {torch.int32: 32, torch.uint32: 32, torch.int64: 64, torch.uint64: 64}
+
+
+def _words(t: torch.Tensor, what: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % what)
+    if t.dtype not in _WORD:
+        raise TypeError("%s must be int32/uint32 (or int64/uint64)" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return _WORD[t.dtype]
+
+
+def _log2(n: int) -> int:
+    if n <= 0 or n & (n - 1):
+        raise ValueError("length %d is not a power of two" % n)
+    return n.bit_length() - 1
+
+
+def default_root(m: int, log2n: int) -> int:
+    """2^(nu/N) mod m: the harmonic of exact order N = 2^log2n (Eq. 5)."""
+    r = ctypes.c_uint64(0)
+    _check(lib.ntt_default_root(int(m), int(log2n), ctypes.byref(r)), "ntt_default_root")
+    return int(r.value)
+
+
+def modulus_order(m: int) -> int:
+    """log2 of the order of 2 modulo m (Prop. 2)."""
+    r = ctypes.c_uint32(0)
+    _check(lib.ntt_modulus_order(int(m), ctypes.byref(r)), "ntt_modulus_order")
+    return int(r.value)
+
+
+def _ntt(fn, name, x, m, root, out, flags, stream):
+    bits = _words(x, "x")
+    N = x.shape[-1]
+    log2n = _log2(N)
+    batch = x.numel() // N if x.numel() else 0
+    if root is None:
+        root = default_root(m, log2n)
+    if out is None:
+        out = torch.empty_like(x)
+    elif _words(out, "out") != bits or out.shape != x.shape:
+        raise ValueError("out must match x in shape and word width")
+    _check(fn(int(m), log2n, int(root), bits, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+              batch, int(flags), _stream(stream)), name)
+    return out
+
+
+def ntt_forward(x: torch.Tensor, m: int, root: int | None = None, out=None, flags: int = 0, stream=None):
+    """Eq. 2 along the last dimension (a power of two), natural order."""
+    return _ntt(lib.ntt_forward, "ntt_forward", x, m, root, out, flags, stream)
+
+
+def ntt_inverse(X: torch.Tensor, m: int, root: int | None = None, out=None, flags: int = 0, stream=None):
+    """Eq. 3 (including N^-1) along the last dimension."""
+    return _ntt(lib.ntt_inverse, "ntt_inverse", X, m, root, out, flags, stream)
+
+
+def conv_circular(f: torch.Tensor, g: torch.Tensor, m: int, root: int | None = None, out=None,
+                  flags: int = 0, stream=None):
+    """Circular convolution of Eq. 1 of two 1-D sequences of equal power-of-two length."""
+    bits = _words(f, "f")
+    if _words(g, "g") != bits or g.shape != f.shape or f.dim() != 1:
+        raise ValueError("f and g must be 1-D with the same length and word width")
+    log2n = _log2(f.numel())
+    if root is None:
+        root = default_root(m, log2n)
+    if out is None:
+        out = torch.empty_like(f)
+    elif _words(out, "out") != bits or out.shape != f.shape:
+        raise ValueError("out must match f")
+    _check(lib.conv_circular(int(m), log2n, int(root), bits, ctypes.c_void_p(f.data_ptr()),
+                             ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(flags),
+                             _stream(stream)), "conv_circular")
+    return out
+
+
+class BatchDesc:
+    """Host-side batch descriptor kept alive between calls (log2n and offsets arrays)."""
+
+    def __init__(self, log2n, offsets):
+        import numpy as np
+        self.log2n = np.ascontiguousarray(np.asarray(log2n, dtype=np.uint8))
+        self.offset = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        if self.log2n.shape != self.offset.shape:
+            raise ValueError("log2n and offsets must have the same length")
+        self.c = _BatchDesc(len(self.log2n),
+                            self.log2n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            self.offset.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+
+
+def conv_batched(f: torch.Tensor, g: torch.Tensor, desc, m: int, root: int = 2, root_log2order: int | None = None,
+                 out=None, flags: int = 0, stream=None):
+    """A batch of independent circular convolutions of uneven power-of-two lengths.
+
+    ``desc`` is a BatchDesc (or a (log2n, offsets) pair).  Item i uses
+    root^(2^(root_log2order - log2n[i])); by default root = 2 with its full order.
+    """
+    if not isinstance(desc, BatchDesc):
+        desc = BatchDesc(*desc)
+    bits = _words(f, "f")
+    if _words(g, "g") != bits or g.shape != f.shape:
+        raise ValueError("f and g must match")
+    if root_log2order is None:
+        root_log2order = modulus_order(m) if root == 2 else None
+        if root_log2order is None:
+            raise ValueError("root_log2order is required when root != 2")
+    if out is None:
+        out = torch.empty_like(f)
+    elif _words(out, "out") != bits or out.shape != f.shape:
+        raise ValueError("out must match f")
+    _check(lib.conv_batched(int(m), int(root), int(root_log2order), bits, ctypes.byref(desc.c),
+                            ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr()), int(flags), _stream(stream)), "conv_batched")
+    return out
+
+
+def release_caches() -> None:
+    lib.ntt_release_caches()

@@ -1,0 +1,477 @@
+// C-ABI of the library: validation, plan and workspace caches, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/nttmi.h"
+#include "launch.hpp"
+#include "numtheory.hpp"
+
+using namespace nttmi;
+
+namespace {
+
+struct Plan {
+    DevPlan dev{};
+    double2* dP = nullptr;
+    double2* dTT = nullptr;
+    double2* dTTi = nullptr;
+};
+
+struct Buf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Caches {
+    std::mutex mu;
+    std::map<std::tuple<int, uint64_t, int, uint64_t>, Plan> plans;   // (dev, m, log2n, root)
+    std::map<std::pair<int, void*>, Buf> work;                        // (dev, stream) -> scratch
+    std::map<std::pair<int, void*>, Buf> flag;                        // (dev, stream) -> range flag
+    std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
+    std::map<uint64_t, int> moduli;                                   // m -> log2 nu or -1
+    std::map<int, int> cu_count;                                      // dev -> CUs
+};
+
+Caches& caches() {
+    static Caches* c = new Caches();  // intentionally never destroyed
+    return *c;
+}
+
+ntt_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return NTT_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return NTT_E_NOMEM;
+    return NTT_E_DEVICE;
+}
+
+ModC make_modc(uint64_t m) {
+    ModC M;
+    M.m = (double)m;
+    M.minv = 1.0 / (double)m;
+    M.C = 6755399441055744.0;  // 1.5 * 2^52
+    M.Cm = M.C * (double)m;    // exact: 3m < 2^26
+    return M;
+}
+
+double2 tw_pair(uint64_t w, uint64_t m) {
+    double2 t;
+    t.x = (double)w;
+    t.y = (double)w / (double)m;
+    return t;
+}
+
+// log2(nu) for a valid modulus (prime, order of 2 a power of two: Sec. II,
+// Prop. 2); -1 otherwise.  Cached.
+int modulus_log2nu(uint64_t m) {
+    Caches& c = caches();
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.moduli.find(m);
+        if (it != c.moduli.end()) return it->second;
+    }
+    int lnu = -1;
+    if (m >= 3 && is_prime64(m)) lnu = log2_order_of_two(m);
+    std::lock_guard<std::mutex> g(c.mu);
+    c.moduli[m] = lnu;
+    return lnu;
+}
+
+ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu) {
+    if (elem_bits != 32 && elem_bits != 64) return NTT_E_ARG;
+    *lnu = modulus_log2nu(m);
+    if (*lnu < 0) return NTT_E_MODULUS;
+    if (elem_bits == 32 && m >= (1ull << 24)) return NTT_E_MODULUS;
+    if (elem_bits == 64 && m >= (1ull << 62)) return NTT_E_MODULUS;
+    return NTT_OK;
+}
+
+// root has exact order 2^k modulo m
+bool root_has_order(uint64_t root, uint32_t k, uint64_t m) {
+    const uint64_t r = root % m;
+    if (k == 0) return r == 1;
+    return powmod64(r, 1ull << (k - 1), m) == m - 1;
+}
+
+ntt_status validate(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, int* lnu) {
+    ntt_status st = check_modulus(m, elem_bits, lnu);
+    if (st != NTT_OK) return st;
+    if ((int)log2n > *lnu) return NTT_E_LENGTH;
+    if (!root_has_order(root, log2n, m)) return NTT_E_ROOT;
+    if (elem_bits == 64) return NTT_E_UNSUPPORTED;
+    if (log2n > (uint32_t)MAX_LOG2N) return NTT_E_UNSUPPORTED;
+    return NTT_OK;
+}
+
+hipError_t upload(double2** d, const std::vector<double2>& h) {
+    hipError_t e = hipMalloc((void**)d, h.size() * sizeof(double2));
+    if (e != hipSuccess) {
+        *d = nullptr;
+        return e;
+    }
+    return hipMemcpy(*d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice);
+}
+
+// Device tables of the plan (m, N = 2^log2n, root): the powers root^e mod m,
+// e < N, which are the harmonics of the digital circle (Eq. 5) generated one
+// factor at a time, and for four-step lengths the twiddles root^(+-t1 u2).
+ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Plan** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
+    const uint64_t r = root % m;
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto key = std::make_tuple(dev, m, (int)log2n, r);
+    auto it = c.plans.find(key);
+    if (it != c.plans.end()) {
+        *out = &it->second;
+        return NTT_OK;
+    }
+    const uint64_t N = 1ull << log2n;
+    std::vector<double2> hP(N);
+    uint64_t x = 1 % m;
+    for (uint64_t e = 0; e < N; ++e) {
+        hP[e] = tw_pair(x, m);
+        x = mulmod64(x, r, m);
+    }
+    Plan p;
+    hipError_t he = upload(&p.dP, hP);
+    if (he == hipSuccess && (int)log2n > SMALL_MAX_LOG2N) {
+        const int la = ((int)log2n + 1) / 2, lb = (int)log2n / 2;
+        const uint64_t A = 1ull << la, B = 1ull << lb;
+        std::vector<double2> tt(N), tti(N);
+        for (uint64_t u2 = 0; u2 < B; ++u2)
+            for (uint64_t t1 = 0; t1 < A; ++t1) {
+                const uint64_t e = (t1 * u2) & (N - 1);
+                tt[u2 * A + t1] = hP[e];
+                tti[u2 * A + t1] = hP[(N - e) & (N - 1)];
+            }
+        he = upload(&p.dTT, tt);
+        if (he == hipSuccess) he = upload(&p.dTTi, tti);
+    }
+    if (he != hipSuccess) {
+        if (p.dP) (void)hipFree(p.dP);
+        if (p.dTT) (void)hipFree(p.dTT);
+        if (p.dTTi) (void)hipFree(p.dTTi);
+        return hip_status(he);
+    }
+    // N^-1 = 2^-n = 2^(nu - n) mod m: the multiplicative inverse of N (Appendix A)
+    const uint64_t ninv = powmod64(2, (1ull << lnu) - log2n, m);
+    p.dev.P = p.dP;
+    p.dev.TT = p.dTT;
+    p.dev.TTi = p.dTTi;
+    p.dev.M = make_modc(m);
+    p.dev.ninv = (double)ninv;
+    p.dev.ninvq = (double)ninv / (double)m;
+    p.dev.logn = (int)log2n;
+    p.dev.nmask = (int)(N - 1);
+    auto ins = c.plans.emplace(key, p);
+    *out = &ins.first->second;
+    return NTT_OK;
+}
+
+// Per-(device, stream) buffer of at least `bytes`.  Growing it first waits for
+// the stream, so no enqueued kernel still uses the old buffer.
+ntt_status get_buf(std::map<std::pair<int, void*>, Buf>& pool, void* stream, size_t bytes, void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
+    std::lock_guard<std::mutex> g(caches().mu);
+    Buf& b = pool[std::make_pair(dev, stream)];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            (void)hipStreamSynchronize((hipStream_t)stream);
+            (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&b.ptr, bytes);
+        if (e != hipSuccess) {
+            b.ptr = nullptr;
+            return hip_status(e);
+        }
+        b.bytes = bytes;
+    }
+    *out = b.ptr;
+    return NTT_OK;
+}
+
+// Device copy of an offsets array, cached by content (uploaded once).
+ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto key = std::make_pair(dev, h);
+    auto it = c.offsets.find(key);
+    if (it == c.offsets.end()) {
+        if (c.offsets.size() >= 256) {
+            (void)hipDeviceSynchronize();
+            for (auto& kv : c.offsets) (void)hipFree(kv.second.ptr);
+            c.offsets.clear();
+        }
+        Buf b;
+        hipError_t e = hipMalloc(&b.ptr, h.size() * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMemcpy(b.ptr, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (b.ptr) (void)hipFree(b.ptr);
+            return hip_status(e);
+        }
+        b.bytes = h.size() * sizeof(uint64_t);
+        it = c.offsets.emplace(key, b).first;
+    }
+    *out = (const uint64_t*)it->second.ptr;
+    return NTT_OK;
+}
+
+int cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    Caches& c = caches();
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.cu_count.find(dev);
+        if (it != c.cu_count.end()) return it->second;
+    }
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+    std::lock_guard<std::mutex> g(c.mu);
+    c.cu_count[dev] = n;
+    return n;
+}
+
+// [a, a+na) and [b, b+nb) in bytes: 0 disjoint, 1 identical start and size, 2 partial
+int overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    if (x + na <= y || y + nb <= x) return 0;
+    if (x == y && na == nb) return 1;
+    return 2;
+}
+
+ntt_status check_range(const void* x, uint64_t n, uint64_t m, void* stream) {
+    void* flag = nullptr;
+    ntt_status st = get_buf(caches().flag, stream, sizeof(uint32_t), &flag);
+    if (st != NTT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_range_check((const uint32_t*)x, n, (uint32_t)m, (uint32_t*)flag, s);
+    uint32_t hflag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e);
+    return hflag ? NTT_E_RANGE : NTT_OK;
+}
+
+// One convolution of length 2^log2n (plan already built) on the stream.
+ntt_status conv_one(const Plan* p, uint32_t log2n, const uint32_t* f, const uint32_t* g, uint32_t* h,
+                    void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if ((int)log2n <= SMALL_MAX_LOG2N) return hip_status(launch_conv_small(log2n, f, g, h, nullptr, 1, p->dev, s));
+    void* ws = nullptr;
+    ntt_status st = get_buf(caches().work, stream, (size_t)2 * sizeof(int32_t) << log2n, &ws);
+    if (st != NTT_OK) return st;
+    return hip_status(launch_conv_fourstep(log2n, f, g, h, 1, 0, (int32_t*)ws, p->dev, s));
+}
+
+ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* x, void* X,
+                   uint32_t batch, uint32_t flags, void* stream) {
+    int lnu = 0;
+    ntt_status st = validate(m, log2n, root, elem_bits, &lnu);
+    if (st != NTT_OK) return st;
+    if (batch == 0) return NTT_OK;
+    if (!x || !X) return NTT_E_ARG;
+    const size_t bytes = ((size_t)batch << log2n) * (elem_bits / 8);
+    if (overlap(x, bytes, X, bytes) == 2) return NTT_E_ARG;
+    if (flags & NTT_FLAG_CHECK_RANGE) {
+        st = check_range(x, (uint64_t)batch << log2n, m, stream);
+        if (st != NTT_OK) return st;
+    }
+    const Plan* p = nullptr;
+    st = get_plan(m, log2n, root, lnu, &p);
+    if (st != NTT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((int)log2n <= SMALL_MAX_LOG2N)
+        return hip_status(launch_ntt_small(log2n, inv, (const uint32_t*)x, (uint32_t*)X, batch, p->dev, s));
+    void* ws = nullptr;
+    st = get_buf(caches().work, stream, ((size_t)batch * sizeof(int32_t)) << log2n, &ws);
+    if (st != NTT_OK) return st;
+    return hip_status(
+        launch_ntt_fourstep(log2n, inv, (const uint32_t*)x, (uint32_t*)X, batch, (int32_t*)ws, p->dev, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+ntt_status ntt_forward(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* x, void* X,
+                       uint32_t batch, uint32_t flags, void* stream) {
+    return ntt_any(false, m, log2n, root, elem_bits, x, X, batch, flags, stream);
+}
+
+ntt_status ntt_inverse(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* X, void* x,
+                       uint32_t batch, uint32_t flags, void* stream) {
+    return ntt_any(true, m, log2n, root, elem_bits, X, x, batch, flags, stream);
+}
+
+ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* f,
+                         const void* g, void* h, uint32_t flags, void* stream) {
+    int lnu = 0;
+    ntt_status st = validate(m, log2n, root, elem_bits, &lnu);
+    if (st != NTT_OK) return st;
+    if (!f || !g || !h) return NTT_E_ARG;
+    const size_t bytes = ((size_t)1 << log2n) * (elem_bits / 8);
+    if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
+    if (flags & NTT_FLAG_CHECK_RANGE) {
+        st = check_range(f, 1ull << log2n, m, stream);
+        if (st == NTT_OK) st = check_range(g, 1ull << log2n, m, stream);
+        if (st != NTT_OK) return st;
+    }
+    const Plan* p = nullptr;
+    st = get_plan(m, log2n, root, lnu, &p);
+    if (st != NTT_OK) return st;
+    return conv_one(p, log2n, (const uint32_t*)f, (const uint32_t*)g, (uint32_t*)h, stream);
+}
+
+ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
+                        const ntt_batch_desc* d, const void* f, const void* g, void* h, uint32_t flags,
+                        void* stream) {
+    int lnu = 0;
+    ntt_status st = check_modulus(m, elem_bits, &lnu);
+    if (st != NTT_OK) return st;
+    if (!d) return NTT_E_ARG;
+    if ((int)root_log2order > lnu) return NTT_E_LENGTH;
+    if (!root_has_order(root, root_log2order, m)) return NTT_E_ROOT;
+    if (d->count == 0) return NTT_OK;
+    if (!d->log2n || !d->offset || !f || !g || !h) return NTT_E_ARG;
+    if (elem_bits == 64) return NTT_E_UNSUPPORTED;
+    const uint32_t cnt = d->count;
+    // items: lengths within the root's order, no two items overlapping
+    std::vector<std::pair<uint64_t, uint64_t>> ext(cnt);
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t n = d->log2n[i];
+        if (n > root_log2order) return NTT_E_LENGTH;
+        if (n > (uint32_t)MAX_LOG2N) return NTT_E_UNSUPPORTED;
+        const uint64_t len = 1ull << n;
+        if (d->offset[i] > (UINT64_MAX >> 3) - len) return NTT_E_ARG;
+        ext[i] = std::make_pair(d->offset[i], d->offset[i] + len);
+        total = std::max(total, d->offset[i] + len);
+    }
+    std::sort(ext.begin(), ext.end());
+    for (uint32_t i = 1; i < cnt; ++i)
+        if (ext[i].first < ext[i - 1].second) return NTT_E_ARG;
+    const size_t bytes = (size_t)total * (elem_bits / 8);
+    if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
+    if (flags & NTT_FLAG_CHECK_RANGE) {
+        // checks the whole extent, gaps between items included
+        st = check_range(f, total, m, stream);
+        if (st == NTT_OK) st = check_range(g, total, m, stream);
+        if (st != NTT_OK) return st;
+    }
+    const uint32_t* F = (const uint32_t*)f;
+    const uint32_t* G = (const uint32_t*)g;
+    uint32_t* H = (uint32_t*)h;
+    hipStream_t s = (hipStream_t)stream;
+
+    // length classes
+    std::map<uint32_t, std::vector<uint64_t>> cls;
+    for (uint32_t i = 0; i < cnt; ++i) cls[d->log2n[i]].push_back(d->offset[i]);
+    const int cus = cu_count();
+    for (auto& kv : cls) {
+        const uint32_t n = kv.first;
+        std::vector<uint64_t>& off = kv.second;
+        const uint64_t item_root = powmod64(root % m, 1ull << (root_log2order - n), m);
+        const Plan* p = nullptr;
+        st = get_plan(m, n, item_root, lnu, &p);
+        if (st != NTT_OK) return st;
+        if (flags & NTT_FLAG_PER_ITEM) {
+            for (uint64_t o : off) {
+                st = conv_one(p, n, F + o, G + o, H + o, stream);
+                if (st != NTT_OK) return st;
+            }
+            continue;
+        }
+        const uint32_t c = (uint32_t)off.size();
+        // contiguous uniform run: offsets base + i N, no table needed
+        bool contiguous = true;
+        for (uint32_t i = 1; i < c && contiguous; ++i) contiguous = off[i] == off[0] + ((uint64_t)i << n);
+        const uint64_t base = contiguous ? off[0] : 0;
+        const uint64_t* doffs = nullptr;
+        if (!contiguous) {
+            st = get_offsets(off, &doffs);
+            if (st != NTT_OK) return st;
+        }
+        if ((int)n <= SMALL_MAX_LOG2N) {
+            st = hip_status(launch_conv_small(n, F + base, G + base, H + base, doffs, c, p->dev, s));
+        } else {
+            // persistent fused form: grid = resident workgroups, bounded by a
+            // 1 GiB scratch budget (2N words per workgroup)
+            const int per_cu = std::max(1, fused_blocks_per_cu(n));
+            uint64_t grid = (uint64_t)std::max(1, cus) * per_cu;
+            const uint64_t per_wg = (uint64_t)2 * sizeof(int32_t) << n;
+            grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));
+            grid = std::min<uint64_t>(grid, c);
+            void* ws = nullptr;
+            st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
+            if (st != NTT_OK) return st;
+            st = hip_status(launch_conv_fused(n, F + base, G + base, H + base, doffs, c, (int32_t*)ws,
+                                              (uint32_t)grid, p->dev, s));
+        }
+        if (st != NTT_OK) return st;
+    }
+    return NTT_OK;
+}
+
+ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t* root) {
+    if (!root) return NTT_E_ARG;
+    const int lnu = modulus_log2nu(m);
+    if (lnu < 0) return NTT_E_MODULUS;
+    if ((int)log2n > lnu) return NTT_E_LENGTH;
+    // 2^(nu/N): the harmonic of exact order N
+    *root = powmod64(2, (1ull << lnu) >> log2n, m);
+    return NTT_OK;
+}
+
+ntt_status ntt_modulus_order(uint64_t m, uint32_t* log2_nu) {
+    if (!log2_nu) return NTT_E_ARG;
+    const int lnu = modulus_log2nu(m);
+    if (lnu < 0) return NTT_E_MODULUS;
+    *log2_nu = (uint32_t)lnu;
+    return NTT_OK;
+}
+
+const char* ntt_status_string(ntt_status s) {
+    switch (s) {
+        case NTT_OK: return "ok";
+        case NTT_E_ARG: return "invalid argument (null pointer, element width, descriptor or overlap)";
+        case NTT_E_MODULUS: return "invalid modulus (not prime, order of 2 not a power of two, or too wide)";
+        case NTT_E_LENGTH: return "length does not divide the order of 2 modulo m";
+        case NTT_E_ROOT: return "root is not of exact order N modulo m";
+        case NTT_E_RANGE: return "an operand is not below m";
+        case NTT_E_NOMEM: return "out of memory";
+        case NTT_E_DEVICE: return "HIP runtime or launch failure";
+        case NTT_E_UNSUPPORTED: return "valid request not supported by this build";
+    }
+    return "unknown status";
+}
+
+void ntt_release_caches(void) {
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c.plans) {
+        if (kv.second.dP) (void)hipFree(kv.second.dP);
+        if (kv.second.dTT) (void)hipFree(kv.second.dTT);
+        if (kv.second.dTTi) (void)hipFree(kv.second.dTTi);
+    }
+    c.plans.clear();
+    for (auto& kv : c.work) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c.work.clear();
+    for (auto& kv : c.flag) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c.flag.clear();
+    for (auto& kv : c.offsets) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c.offsets.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and
+validates arguments on the host (these calls return before touching a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nttmi.h")
+LIB = os.path.join(ROOT, "paper_1005_1497_amd", "libnttmi.so")
+
+M = 13631489
+BAD = ctypes.c_void_p(0x100000)   # never dereferenced: every call below fails validation first
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)) - {"defined"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libnttmi.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB)
+    U64, U32, I32, VP = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
+    L.conv_circular.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, VP]
+    L.conv_circular.restype = I32
+    for n in ("ntt_forward", "ntt_inverse"):
+        getattr(L, n).argtypes = [U64, U32, U64, U32, VP, VP, U32, U32, VP]
+        getattr(L, n).restype = I32
+    L.ntt_default_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
+    L.ntt_default_root.restype = I32
+    L.ntt_modulus_order.argtypes = [U64, ctypes.POINTER(U32)]
+    L.ntt_modulus_order.restype = I32
+    L.ntt_status_string.argtypes = [I32]
+    L.ntt_status_string.restype = ctypes.c_char_p
+    return L
+
+
+def test_header_declares_the_four_calls():
+    fns = header_functions()
+    for name in ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched"):
+        assert name in fns
+
+
+def test_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for s in range(9):
+        assert lib.ntt_status_string(s)
+    assert b"unknown" in lib.ntt_status_string(99)
+
+
+def test_modulus_order(lib):
+    out = ctypes.c_uint32(0)
+    for m, lognu in ((641, 6), (2424833, 10), (319489, 12), (13631489, 19), (31065037602817, 18)):
+        assert lib.ntt_modulus_order(m, ctypes.byref(out)) == 0
+        assert out.value == lognu
+    assert lib.ntt_modulus_order(341, ctypes.byref(out)) == 2        # composite (Sec. II)
+    assert lib.ntt_modulus_order(2 ** 32 + 1, ctypes.byref(out)) == 2  # F_5 composite
+    assert lib.ntt_modulus_order(7, ctypes.byref(out)) == 2          # order of 2 is 3
+
+
+def test_default_root_closed_forms(lib):
+    r = ctypes.c_uint64(0)
+    assert lib.ntt_default_root(M, 10, ctypes.byref(r)) == 0 and r.value == pow(2, 512, M)
+    assert lib.ntt_default_root(M, 16, ctypes.byref(r)) == 0 and r.value == 256
+    assert lib.ntt_default_root(M, 19, ctypes.byref(r)) == 0 and r.value == 2
+    assert lib.ntt_default_root(M, 0, ctypes.byref(r)) == 0 and r.value == 1
+    assert lib.ntt_default_root(M, 20, ctypes.byref(r)) == 3          # NTT_E_LENGTH
+
+
+def test_conv_validation_errors(lib):
+    c = lib.conv_circular
+    assert c(341, 2, 4, 32, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 2          # modulus composite
+    assert c(M, 20, 2, 32, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 3           # N does not divide nu
+    assert c(M, 10, 2, 32, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 4           # 2 has order 2^19
+    assert c(M, 10, pow(2, 1024, M), 32, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 4  # order 512
+    assert c(M, 10, pow(2, 512, M), 16, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 1   # elem_bits
+    assert c(M, 10, pow(2, 512, M), 32, None, BAD, ctypes.c_void_p(0x200000), 0, None) == 1  # null
+    # partial overlap of h with f
+    assert c(M, 10, pow(2, 512, M), 32, BAD, ctypes.c_void_p(0x900000), ctypes.c_void_p(0x100000 + 64),
+             0, None) == 1
+    # a 32-bit word cannot carry a 45-bit modulus
+    assert c(31065037602817, 10, pow(2, 256, 31065037602817), 32, BAD, BAD, ctypes.c_void_p(0x200000),
+             0, None) == 2
+
+
+def test_ntt_validation_errors(lib):
+    for fn in (lib.ntt_forward, lib.ntt_inverse):
+        assert fn(641, 7, 2, 32, BAD, BAD, 1, 0, None) == 3          # 641 allows N <= 64
+        assert fn(641, 6, 3, 32, BAD, BAD, 1, 0, None) == 4
+        assert fn(M, 4, pow(2, 2 ** 15, M), 32, BAD, BAD, 0, 0, None) == 0  # empty batch: nothing to do
+        assert fn(M, 4, pow(2, 2 ** 15, M), 32, None, BAD, 1, 0, None) == 1

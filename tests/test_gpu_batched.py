@@ -1,0 +1,89 @@
+"""GPU parity of the batched forms: the fused batch equals the same items run
+one by one, and the oracle on sampled items."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import seeded_inputs as si
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+M = 13631489
+
+
+@pytest.fixture(scope="module")
+def nt():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1005_1497_amd as nt
+    return nt
+
+
+def _item_root(n):
+    return pow(2, 1 << (19 - n), M)
+
+
+@pytest.mark.parametrize("n,count", [(4, 300), (8, 70), (12, 5), (13, 9), (16, 6), (16, 700)])
+def test_uniform_batch_matches_oracle(nt, n, count):
+    w = si.Workload("t", M, (n,) * count, 32, M, 11 + n)
+    f, g = si.operands(w)
+    desc = nt.BatchDesc([n] * count, si.offsets([n] * count))
+    h = host(nt.conv_batched(dev(f), dev(g), desc, M))
+    N = 1 << n
+    rng = np.random.default_rng(n)
+    items = sorted(set([0, count - 1] + list(rng.integers(0, count, 3))))
+    for i in items:
+        fi, gi = f[i * N:(i + 1) * N], g[i * N:(i + 1) * N]
+        if n <= 13:
+            assert np.array_equal(h[i * N:(i + 1) * N], oracle.conv_direct(fi, gi, M).astype(np.uint32)), i
+        else:
+            idx = rng.integers(0, N, 24)
+            assert np.array_equal(h[i * N + idx], oracle.conv_entries(fi, gi, M, idx).astype(np.uint32)), i
+    # the same batch, one item per launch sequence
+    h1 = host(nt.conv_batched(dev(f), dev(g), desc, M, flags=nt.FLAG_PER_ITEM))
+    assert np.array_equal(h, h1)
+
+
+def test_uneven_batch_matches_per_item(nt):
+    w = si.uneven_batch(count=60, seed=4)
+    f, g = si.operands(w)
+    offs = si.offsets(w.log2n)
+    desc = nt.BatchDesc(w.log2n, offs)
+    h = host(nt.conv_batched(dev(f), dev(g), desc, M))
+    h1 = host(nt.conv_batched(dev(f), dev(g), desc, M, flags=nt.FLAG_PER_ITEM))
+    assert np.array_equal(h, h1)
+    for i, n in enumerate(w.log2n):
+        N = 1 << n
+        o = int(offs[i])
+        fi, gi, hi = f[o:o + N], g[o:o + N], h[o:o + N]
+        if n <= 10:
+            assert np.array_equal(hi, oracle.conv_direct(fi, gi, M).astype(np.uint32)), (i, n)
+        else:
+            idx = np.array([0, N - 1, N // 3])
+            assert np.array_equal(hi[idx], oracle.conv_entries(fi, gi, M, idx).astype(np.uint32)), (i, n)
+
+
+def test_gapped_offsets_and_empty(nt):
+    # items out of order with gaps between them
+    log2n = [5, 9, 3, 9, 13]
+    offs = [9000, 0, 700, 20000, 40000]
+    total = 40000 + (1 << 13) + 5
+    f = si.uniform(1, total, M)
+    g = si.uniform(2, total, M)
+    out = dev(np.zeros(total, np.uint32))
+    nt.conv_batched(dev(f), dev(g), nt.BatchDesc(log2n, offs), M, out=out)
+    h = host(out)
+    for n, o in zip(log2n, offs):
+        N = 1 << n
+        assert np.array_equal(h[o:o + N], oracle.conv_direct(f[o:o + N], g[o:o + N], M).astype(np.uint32))
+    assert h[600] == 0 and h[total - 1] == 0        # gaps untouched
+    nt.conv_batched(dev(f), dev(g), nt.BatchDesc([], []), M)  # empty batch
+
+
+def test_overlapping_items_rejected(nt):
+    f = dev(np.zeros(4096, np.uint32))
+    with pytest.raises(nt.NttError) as e:
+        nt.conv_batched(f, f, nt.BatchDesc([10, 10], [0, 512]), M)
+    assert e.value.name == "NTT_E_ARG"
