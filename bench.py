@@ -1,0 +1,176 @@
+"""Benchmark: a batch of 4096 exact circular convolutions of N = 2^16 modulo
+m = 13631489 (root 2^8 = 256 of exact order 2^16), one GPU.
+
+A step is one conv_batched call over the whole batch (forward transforms of f
+and g, pointwise product, inverse, N^-1, canonical store): a single fused
+persistent kernel launch.  Operands are seeded synthetic uint32 words uniform
+in [0, m), resident in HBM before timing.
+
+Prints one JSON line (see the README for the fields); diagnostic lines go to
+stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact convolutions/s and HBM GB/s (% roofline), batched N=2^16; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# fp64 vector lanes: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 FMA-or-add per second
+# (the published 78.6 TFLOP/s fp64 vector counts an FMA as two flops)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+N_LOG2 = 16
+COUNT = 4096
+
+
+def alg_ops_per_conv(n_log2: int) -> int:
+    """fp64 lane operations of the exact arithmetic per convolution: three
+    transforms of (N/2) log2 N butterflies at 5 ops (3-FMA modular product + two
+    adds), plus N pointwise products at 7 ops (N^-1 folded in)."""
+    N = 1 << n_log2
+    return 5 * 3 * (N // 2) * n_log2 + 7 * N
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(f, g, m, N, budget_s=12.0):
+    """The oracle (direct O(N^2) sum of Eq. 1, plain C, all host threads) on a
+    bounded sample of items of the same workload."""
+    import oracle
+    threads = oracle.threads()
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        o = done * N
+        oracle.conv_direct(f[o:o + N], g[o:o + N], m)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or done >= 64 or el / done * (done + 1) > 2.5 * budget_s:
+            break
+    return {"value": done / el, "unit": "conv/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of the %d items (N=%d), direct O(N^2) sum, %.1f s" % (done, COUNT, N, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the batch would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1005_1497_amd as nt
+    import seeded_inputs as si
+
+    w = si.batch_n65536(COUNT)
+    m, N = w.m, 1 << N_LOG2
+    t0 = time.perf_counter()
+    f_h, g_h = si.operands(w)
+    log("inputs drawn in %.1f s" % (time.perf_counter() - t0))
+    dev = torch.device("cuda", 0)
+    f = torch.from_numpy(f_h.view(np.int32)).to(dev)
+    g = torch.from_numpy(g_h.view(np.int32)).to(dev)
+    h = torch.empty_like(f)
+    desc = nt.BatchDesc([N_LOG2] * COUNT, si.offsets([N_LOG2] * COUNT))
+    stream = torch.cuda.current_stream()
+
+    def step(flags=0):
+        nt.conv_batched(f, g, desc, m, out=h, flags=flags, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in evs])   # ms, one fused launch each
+    log("timed %d steps: wall %.3f s, launch mean %.3f ms" % (args.steps, wall, per.mean()))
+
+    # sampled parity of the timed output against the oracle
+    import oracle
+    hh = h.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(0)
+    ok = True
+    for item in (0, COUNT // 2, COUNT - 1):
+        o = item * N
+        idx = rng.integers(0, N, 8)
+        ref = oracle.conv_entries(f_h[o:o + N], g_h[o:o + N], m, idx)
+        ok &= bool(np.array_equal(hh[o + idx], ref.astype(np.uint32)))
+    if not ok:
+        log("PARITY FAILURE in the timed output")
+
+    forms = {}
+    if not args.no_forms:
+        # the plain one-launch-sequence-per-convolution form on the same GPU
+        step(nt.FLAG_PER_ITEM)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(nt.FLAG_PER_ITEM)
+        torch.cuda.synchronize()
+        forms["per_item_ms_per_step"] = (time.perf_counter() - t1) * 1e3
+        forms["per_item_conv_per_s"] = COUNT / (forms["per_item_ms_per_step"] / 1e3)
+
+    value = COUNT * args.steps / wall
+    ms = wall / args.steps * 1e3
+    alg_bytes = 12 * N * COUNT                     # read f, read g, write h (4-byte words)
+    launch_s = per.mean() / 1e3
+    alg_ops = alg_ops_per_conv(N_LOG2) * COUNT
+    achieved_tops = alg_ops / launch_s / 1e12
+    hbm_gbs = alg_bytes / launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "conv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "count": COUNT, "n": N, "m": m, "root": 256,
+                   "words": "u32", "parallelism": "batch (one workgroup per convolution)"},
+        "elements_per_s": value * N,
+        "hbm_gbs_algorithmic": hbm_gbs,
+        "hbm_frac_of_8tbs": hbm_gbs / HBM_PEAK_GBS,
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_conv_fused<16>", "alg_ops_per_launch": alg_ops,
+                     "launch_ms": per.mean()},
+        "hbm_roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": hbm_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
+        "forms": forms,
+        "parity_sampled": ok,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(f_h, g_h, m, N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -18,8 +19,8 @@ namespace {
 struct Plan {
     DevPlan dev{};
     double2* dP = nullptr;
-    double2* dTT = nullptr;
-    double2* dTTi = nullptr;
+    double* dTT = nullptr;
+    double* dTTi = nullptr;
 };
 
 struct Buf {
@@ -106,13 +107,14 @@ ntt_status validate(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bit
     return NTT_OK;
 }
 
-hipError_t upload(double2** d, const std::vector<double2>& h) {
-    hipError_t e = hipMalloc((void**)d, h.size() * sizeof(double2));
+template <class T>
+hipError_t upload(T** d, const std::vector<T>& h) {
+    hipError_t e = hipMalloc((void**)d, h.size() * sizeof(T));
     if (e != hipSuccess) {
         *d = nullptr;
         return e;
     }
-    return hipMemcpy(*d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice);
+    return hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
 // Device tables of the plan (m, N = 2^log2n, root): the powers root^e mod m,
@@ -142,12 +144,12 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     if (he == hipSuccess && (int)log2n > SMALL_MAX_LOG2N) {
         const int la = ((int)log2n + 1) / 2, lb = (int)log2n / 2;
         const uint64_t A = 1ull << la, B = 1ull << lb;
-        std::vector<double2> tt(N), tti(N);
+        std::vector<double> tt(N), tti(N);
         for (uint64_t u2 = 0; u2 < B; ++u2)
             for (uint64_t t1 = 0; t1 < A; ++t1) {
                 const uint64_t e = (t1 * u2) & (N - 1);
-                tt[u2 * A + t1] = hP[e];
-                tti[u2 * A + t1] = hP[(N - e) & (N - 1)];
+                tt[u2 * A + t1] = hP[e].x;
+                tti[u2 * A + t1] = hP[(N - e) & (N - 1)].x;
             }
         he = upload(&p.dTT, tt);
         if (he == hipSuccess) he = upload(&p.dTTi, tti);
@@ -407,7 +409,12 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
         } else {
             // persistent fused form: grid = resident workgroups, bounded by a
             // 1 GiB scratch budget (2N words per workgroup)
-            const int per_cu = std::max(1, fused_blocks_per_cu(n));
+            // tuning override: NTTMI_FUSED_WG_PER_CU caps resident workgroups per CU
+            int per_cu = std::max(1, fused_blocks_per_cu(n));
+            if (const char* e = std::getenv("NTTMI_FUSED_WG_PER_CU")) {
+                const int cap = std::atoi(e);
+                if (cap > 0) per_cu = std::min(per_cu, cap);
+            }
             uint64_t grid = (uint64_t)std::max(1, cus) * per_cu;
             const uint64_t per_wg = (uint64_t)2 * sizeof(int32_t) << n;
             grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));

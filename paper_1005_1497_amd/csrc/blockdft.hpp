@@ -140,14 +140,16 @@ __device__ __forceinline__ int tw_index(int eL, int lshift, int nmask) {
     return INV ? ((-idx) & nmask) : idx;
 }
 
-// Full length-L transform of the block.  On entry v[i] holds the pass-0 input
+// Full length-L transform of the block.  `twf(v, p, Ns, k)` multiplies v[r]
+// by w_{16 Ns}^(r k) (or its inverse) for r < 16: the inter-pass twiddles of
+// pass p.  On entry v[i] holds the pass-0 input
 // at position Blk::pos0(j, i) of sequence s (reduced); on exit v[i] holds the
 // output at Blk::posL(j, i).  `ldsbuf` must be free on entry and is free on
 // exit.  P is the power table of the item's N-th root (N = L << lshift).
-template <int L, int S, int ORD, bool INV>
-__device__ __forceinline__ void block_dft(double* v, double* ldsbuf, int s, int j,
-                                          const double2* __restrict__ P, int lshift, int nmask,
-                                          const ModC& M) {
+template <int L, int S, int ORD, bool INV, class TWF>
+__device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, int j,
+                                             const double2* __restrict__ P, int lshift, int nmask,
+                                             const ModC& M, TWF twf) {
     using B = Blk<L, S, ORD>;
     constexpr int E = B::E;
     // keep the uniform twiddle loads inside this transform (not hoisted into
@@ -182,12 +184,37 @@ __device__ __forceinline__ void block_dft(double* v, double* ldsbuf, int s, int 
         for (int r = 0; r < 16; ++r) v[r] = ldsbuf[B::lds(s, j + r * (L / 16))];
         __syncthreads();
         // inter-pass twiddles w_{16 Ns}^(r k) = w_L^((L/(16 Ns)) r k), k = j mod Ns
-        const int k = j & (Ns - 1);
-        const int step = (L / (16 * Ns)) * k;
-        mul_twiddles<16>(v, M, [&](int r) { return P[tw_index<INV>(step * r, lshift, nmask)]; });
+        twf(v, p, Ns, j & (Ns - 1));
         dft_reg<16>(v, twE, 1, M);
         Ns *= 16;
     }
+}
+
+// Per-pass twiddle tables of a length-L transform, laid out [pass][k][r] with
+// entry w_{16 Ns}^(r k) (k < Ns, r < 16), so that one work item's sixteen
+// twiddles are contiguous.  Rows are padded to 17 entries so that lanes with
+// consecutive k read different LDS banks.  Pass p >= 1 has Ns = R0 16^(p-1).
+template <int L>
+struct PassTab {
+    using B = Blk<L, 1, SEQ_FAST>;
+    static constexpr int ROW = 17;
+    static constexpr int ns(int p) { return p <= 0 ? 1 : (p == 1 ? B::R0 : 16 * ns(p - 1)); }
+    static constexpr int off(int p) { return p <= 1 ? 0 : off(p - 1) + ROW * ns(p - 1); }
+    static constexpr int SIZE = B::NP > 1 ? off(B::NP) : 1;   // entries of all passes
+    // exponent of w_L of entry (p, k, r)
+    __device__ static __forceinline__ int expo(int p, int k, int r) { return (L / (16 * ns(p))) * r * k; }
+};
+
+// block_dft_tw with the inter-pass twiddles read from the global power table
+// (software-pipelined loads).
+template <int L, int S, int ORD, bool INV>
+__device__ __forceinline__ void block_dft(double* v, double* ldsbuf, int s, int j,
+                                          const double2* __restrict__ P, int lshift, int nmask,
+                                          const ModC& M) {
+    block_dft_tw<L, S, ORD, INV>(v, ldsbuf, s, j, P, lshift, nmask, M, [&](double* vv, int, int Ns, int k) {
+        const int step = (L / (16 * Ns)) * k;
+        mul_twiddles<16>(vv, M, [&](int r) { return P[tw_index<INV>(step * r, lshift, nmask)]; });
+    });
 }
 
 }  // namespace nttmi

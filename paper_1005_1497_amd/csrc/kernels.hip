@@ -107,54 +107,202 @@ struct FS {
     using BC = Blk<Bn, SC, SEQ_FAST>;
     using BR = Blk<A, SR, POS_FAST>;
     using BRS = Blk<A, SR, SEQ_FAST>;      // rows read/written at stride B (natural-order NTT)
-    static constexpr int LDS = (BC::LDS_DOUBLES > BR::LDS_DOUBLES ? BC::LDS_DOUBLES : BR::LDS_DOUBLES) >
-                                       BRS::LDS_DOUBLES
-                                   ? (BC::LDS_DOUBLES > BR::LDS_DOUBLES ? BC::LDS_DOUBLES : BR::LDS_DOUBLES)
-                                   : BRS::LDS_DOUBLES;
+    static constexpr int mx(int a, int b) { return a > b ? a : b; }
+    static constexpr int XCH = mx(mx(BC::LDS_DOUBLES, BR::LDS_DOUBLES), BRS::LDS_DOUBLES);
+};
+
+// Buffer resource over [p, p + bytes) (raw, untyped; out-of-range reads
+// return 0 and out-of-range writes are dropped).  Accesses take a per-lane
+// byte offset and a wave-uniform byte offset, so that the strided accesses of
+// a work item cost no per-element address arithmetic.
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000)) {}
+    __device__ __forceinline__ uint32_t ld32(uint32_t v, uint32_t s) const {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+    }
+    __device__ __forceinline__ int32_t ldi32(uint32_t v, uint32_t s) const {
+        return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+    }
+    __device__ __forceinline__ double ld64f(uint32_t v, uint32_t s) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    __device__ __forceinline__ void st32(uint32_t x, uint32_t v, uint32_t s) const {
+        __builtin_amdgcn_raw_buffer_store_b32(x, r, v, s, 0);
+    }
+};
+
+// Shared-memory layout of a four-step workgroup: the pass exchange buffer and
+// the per-pass twiddle tables of the column (length B) and row (length A)
+// transforms, forward and inverse (w only; w/m is formed at use).
+template <int LOGN>
+struct FSLds {
+    using G = FS<LOGN>;
+    static constexpr bool SAME = (G::A == G::Bn);
+    static constexpr int TC = PassTab<G::Bn>::SIZE;
+    static constexpr int TR = PassTab<G::A>::SIZE;
+    static constexpr int WORDS = G::XCH + 2 * TC + (SAME ? 0 : 2 * TR);
+    double* xch;
+    const double* colf;
+    const double* coli;
+    const double* rowf;
+    const double* rowi;
+};
+
+template <int L, bool INV>
+__device__ __forceinline__ void fill_pass_tab(double* t, const DevPlan& p, int logn) {
+    using PT = PassTab<L>;
+    using B = Blk<L, 1, SEQ_FAST>;
+    const int lshift = logn - B::l;
+    const int nmask = (1 << logn) - 1;
+#pragma unroll
+    for (int q = 1; q < B::NP; ++q) {
+        const int cnt = 16 * PT::ns(q);
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const int k = e >> 4, r = e & 15;
+            t[PT::off(q) + k * PT::ROW + r] = p.P[tw_index<INV>(PT::expo(q, k, r), lshift, nmask)].x;
+        }
+    }
+}
+
+// Fills the twiddle tables; ends with a barrier.
+template <int LOGN>
+__device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p) {
+    using G = FS<LOGN>;
+    using FL = FSLds<LOGN>;
+    FL L;
+    L.xch = lds;
+    double* t = lds + G::XCH;
+    fill_pass_tab<G::Bn, false>(t, p, LOGN);
+    fill_pass_tab<G::Bn, true>(t + FL::TC, p, LOGN);
+    L.colf = t;
+    L.coli = t + FL::TC;
+    if (FL::SAME) {
+        L.rowf = L.colf;
+        L.rowi = L.coli;
+    } else {
+        fill_pass_tab<G::A, false>(t + 2 * FL::TC, p, LOGN);
+        fill_pass_tab<G::A, true>(t + 2 * FL::TC + FL::TR, p, LOGN);
+        L.rowf = t + 2 * FL::TC;
+        L.rowi = t + 2 * FL::TC + FL::TR;
+    }
+    __syncthreads();
+    return L;
+}
+
+// Inter-pass twiddles of a length-L transform from its shared pass table.
+template <int L>
+struct TwTab {
+    const double* t;
+    ModC M;
+    __device__ __forceinline__ void operator()(double* v, int p, int, int k) const {
+        const double* b = t + PassTab<L>::off(p) + PassTab<L>::ROW * k;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = mulmod_var(v[r], b[r], M);
+    }
 };
 
 // Column phase, forward: length-B transforms of columns c0..c0+SC of x
 // (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
+// Positions of a work item are j + const(i), so every access is a buffer
+// access with one per-lane offset and a compile-time uniform offset.
 template <int LOGN>
-__device__ __forceinline__ void col_fwd_block(const uint32_t* x, int32_t* Y, int c0, const DevPlan& p,
-                                              double* lds) {
+struct ColIn {
+    uint32_t w[FS<LOGN>::BC::E];
+};
+
+// Raw loads of a forward column block (issued ahead of its transform).
+template <int LOGN>
+__device__ __forceinline__ ColIn<LOGN> col_fwd_load(const uint32_t* x, int c0) {
+    using G = FS<LOGN>;
+    using B = typename G::BC;
+    int s, j;
+    B::item(threadIdx.x, s, j);
+    const Buf bx(x, G::N * 4u);
+    ColIn<LOGN> in;
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) in.w[i] = bx.ld32((c0 + s + G::A * j) * 4u, G::A * (B::pos0(0, i)) * 4u);
+    return in;
+}
+
+template <int LOGN>
+__device__ __forceinline__ void col_fwd_compute(const ColIn<LOGN>& in, int32_t* Y, int c0, const DevPlan& p,
+                                                const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int t1 = c0 + s;
+    const Buf by(Y, G::N * 4u), bt(p.TT, G::N * 8u);
     double v[B::E];
+    // four-step twiddles, loaded ahead of the transform
+    double tw4[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)x[t1 + (size_t)G::A * B::pos0(j, i)], M);
-    block_dft<G::Bn, G::SC, SEQ_FAST, false>(v, lds, s, j, p.P, G::la, G::N - 1, M);
-    mul_twiddles<B::E>(v, M, [&](int i) { return p.TT[(size_t)B::posL(j, i) * G::A + t1]; });
+    for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f((j * G::A + t1) * 8u, B::posL(0, i) * G::A * 8u);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) Y[(size_t)B::posL(j, i) * G::A + t1] = to_i32(v[i]);
+    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)in.w[i], M);
+    block_dft_tw<G::Bn, G::SC, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::la, G::N - 1, M, TwTab<G::Bn>{L.colf, M});
+#pragma unroll
+    for (int i = 0; i < B::E; ++i)
+        by.st32((uint32_t)to_i32(mulmod_var(v[i], tw4[i], M)), (j * G::A + t1) * 4u, B::posL(0, i) * G::A * 4u);
+}
+
+// Column phase, forward: length-B transforms of columns c0..c0+SC of x
+// (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
+// Positions of a work item are j + const(i), so every access is a buffer
+// access with one per-lane offset and a compile-time uniform offset.
+template <int LOGN>
+__device__ __forceinline__ void col_fwd_block(const uint32_t* x, int32_t* Y, int c0, const DevPlan& p,
+                                              const FSLds<LOGN>& L) {
+    col_fwd_compute<LOGN>(col_fwd_load<LOGN>(x, c0), Y, c0, p, L);
 }
 
 // Row phase of a convolution: for rows r0..r0+SR, forward(f row), forward(g
 // row), product with N^-1, inverse, times w^-(t1 u2), back into Yf.
 template <int LOGN>
-__device__ __forceinline__ void row_conv_block(int32_t* Yf, const int32_t* Yg, int r0, const DevPlan& p,
-                                               double* lds) {
+struct RowIn {
+    int32_t f[FS<LOGN>::BR::E];
+    int32_t g[FS<LOGN>::BR::E];
+};
+
+template <int LOGN>
+__device__ __forceinline__ RowIn<LOGN> row_conv_load(const int32_t* Yf, const int32_t* Yg, int r0) {
+    using G = FS<LOGN>;
+    using B = typename G::BR;
+    int s, j;
+    B::item(threadIdx.x, s, j);
+    const Buf bf(Yf, G::N * 4u), bg(Yg, G::N * 4u);
+    const uint32_t rowoff = (uint32_t)((r0 + s) * G::A + j);
+    RowIn<LOGN> in;
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) in.f[i] = bf.ldi32(rowoff * 4u, B::pos0(0, i) * 4u);
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) in.g[i] = bg.ldi32(rowoff * 4u, B::pos0(0, i) * 4u);
+    return in;
+}
+
+template <int LOGN>
+__device__ __forceinline__ void row_conv_compute(const RowIn<LOGN>& in, int32_t* Yf, int r0, const DevPlan& p,
+                                                 const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BR;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    int32_t* rf = Yf + (size_t)u2 * G::A;
-    const int32_t* rg = Yg + (size_t)u2 * G::A;
+    const Buf bf(Yf, G::N * 4u), bt(p.TTi, G::N * 8u);
+    const uint32_t rowoff = (uint32_t)(u2 * G::A + j);
     double F[B::E], v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(rf[B::pos0(j, i)]);
-    block_dft<G::A, G::SR, POS_FAST, false>(v, lds, s, j, p.P, G::lb, G::N - 1, M);
+    for (int i = 0; i < B::E; ++i) v[i] = from_i32(in.f[i]);
+    block_dft_tw<G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowf, M});
 #pragma unroll
     for (int i = 0; i < B::E; ++i) F[i] = v[i];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(rg[B::pos0(j, i)]);
-    block_dft<G::A, G::SR, POS_FAST, false>(v, lds, s, j, p.P, G::lb, G::N - 1, M);
+    for (int i = 0; i < B::E; ++i) v[i] = from_i32(in.g[i]);
+    block_dft_tw<G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowf, M});
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
         const double gs = mulmod(v[i], p.ninv, p.ninvq, M);
@@ -162,113 +310,153 @@ __device__ __forceinline__ void row_conv_block(int32_t* Yf, const int32_t* Yg, i
     }
     if (B::R0 != B::RL) {
 #pragma unroll
-        for (int i = 0; i < B::E; ++i) lds[B::lds(s, B::posL(j, i))] = v[i];
+        for (int i = 0; i < B::E; ++i) L.xch[B::lds(s, B::posL(j, i))] = v[i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < B::E; ++i) v[i] = lds[B::lds(s, B::pos0(j, i))];
+        for (int i = 0; i < B::E; ++i) v[i] = L.xch[B::lds(s, B::pos0(j, i))];
         __syncthreads();
     }
-    block_dft<G::A, G::SR, POS_FAST, true>(v, lds, s, j, p.P, G::lb, G::N - 1, M);
-    mul_twiddles<B::E>(v, M, [&](int i) { return p.TTi[(size_t)u2 * G::A + B::posL(j, i)]; });
+    double tw4[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) rf[B::posL(j, i)] = to_i32(v[i]);
+    for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f(rowoff * 8u, B::posL(0, i) * 8u);
+    block_dft_tw<G::A, G::SR, POS_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowi, M});
+#pragma unroll
+    for (int i = 0; i < B::E; ++i)
+        bf.st32((uint32_t)to_i32(mulmod_var(v[i], tw4[i], M)), rowoff * 4u, B::posL(0, i) * 4u);
+}
+
+template <int LOGN>
+__device__ __forceinline__ void row_conv_block(int32_t* Yf, const int32_t* Yg, int r0, const DevPlan& p,
+                                               const FSLds<LOGN>& L) {
+    row_conv_compute<LOGN>(row_conv_load<LOGN>(Yf, Yg, r0), Yf, r0, p, L);
 }
 
 // Column phase, inverse: length-B inverse transforms of scratch columns,
 // optional N^-1, canonical store to x[t1 + A t2].
+template <int LOGN>
+struct ColInvIn {
+    int32_t w[FS<LOGN>::BC::E];
+};
+
+template <int LOGN>
+__device__ __forceinline__ ColInvIn<LOGN> col_inv_load(const int32_t* Y, int c0) {
+    using G = FS<LOGN>;
+    using B = typename G::BC;
+    int s, j;
+    B::item(threadIdx.x, s, j);
+    const Buf by(Y, G::N * 4u);
+    ColInvIn<LOGN> in;
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) in.w[i] = by.ldi32((j * G::A + c0 + s) * 4u, B::pos0(0, i) * G::A * 4u);
+    return in;
+}
+
 template <int LOGN, bool SCALE>
-__device__ __forceinline__ void col_inv_block(const int32_t* Y, uint32_t* x, int c0, const DevPlan& p,
-                                              double* lds) {
+__device__ __forceinline__ void col_inv_compute(const ColInvIn<LOGN>& in, uint32_t* x, int c0, const DevPlan& p,
+                                                const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
-    const int t1 = c0 + s;
+    const Buf bx(x, G::N * 4u);
+    const uint32_t off = (uint32_t)(j * G::A + c0 + s);
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(Y[(size_t)B::pos0(j, i) * G::A + t1]);
-    block_dft<G::Bn, G::SC, SEQ_FAST, true>(v, lds, s, j, p.P, G::la, G::N - 1, M);
+    for (int i = 0; i < B::E; ++i) v[i] = from_i32(in.w[i]);
+    block_dft_tw<G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M, TwTab<G::Bn>{L.coli, M});
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
         const double y = SCALE ? mulmod(v[i], p.ninv, p.ninvq, M) : v[i];
-        x[t1 + (size_t)G::A * B::posL(j, i)] = canon_u32(y, M);
+        bx.st32(canon_u32(y, M), off * 4u, B::posL(0, i) * G::A * 4u);
     }
+}
+
+template <int LOGN, bool SCALE>
+__device__ __forceinline__ void col_inv_block(const int32_t* Y, uint32_t* x, int c0, const DevPlan& p,
+                                              const FSLds<LOGN>& L) {
+    col_inv_compute<LOGN, SCALE>(col_inv_load<LOGN>(Y, c0), x, c0, p, L);
 }
 
 // Row phase of the natural-order forward transform: X[u2 + B u1].
 template <int LOGN>
 __device__ __forceinline__ void row_fwd_nat_block(const int32_t* Y, uint32_t* X, int r0, const DevPlan& p,
-                                                  double* lds) {
+                                                  const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BRS;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
+    const Buf by(Y, G::N * 4u), bx(X, G::N * 4u);
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(Y[(size_t)u2 * G::A + B::pos0(j, i)]);
-    block_dft<G::A, G::SR, SEQ_FAST, false>(v, lds, s, j, p.P, G::lb, G::N - 1, M);
+    for (int i = 0; i < B::E; ++i) v[i] = from_i32(by.ldi32((u2 * G::A + j) * 4u, B::pos0(0, i) * 4u));
+    block_dft_tw<G::A, G::SR, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowf, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) X[u2 + (size_t)G::Bn * B::posL(j, i)] = canon_u32(v[i], M);
+    for (int i = 0; i < B::E; ++i) bx.st32(canon_u32(v[i], M), (u2 + G::Bn * j) * 4u, G::Bn * B::posL(0, i) * 4u);
 }
 
 // Row phase of the natural-order inverse transform: from X[u2 + B u1] to
 // scratch rows, times w^-(t1 u2).
 template <int LOGN>
 __device__ __forceinline__ void row_inv_nat_block(const uint32_t* X, int32_t* Y, int r0, const DevPlan& p,
-                                                  double* lds) {
+                                                  const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BRS;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
+    const Buf bx(X, G::N * 4u), by(Y, G::N * 4u), bt(p.TTi, G::N * 8u);
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)X[u2 + (size_t)G::Bn * B::pos0(j, i)], M);
-    block_dft<G::A, G::SR, SEQ_FAST, true>(v, lds, s, j, p.P, G::lb, G::N - 1, M);
-    mul_twiddles<B::E>(v, M, [&](int i) { return p.TTi[(size_t)u2 * G::A + B::posL(j, i)]; });
+    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)bx.ld32((u2 + G::Bn * j) * 4u, G::Bn * B::pos0(0, i) * 4u), M);
+    double tw4[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) Y[(size_t)u2 * G::A + B::posL(j, i)] = to_i32(v[i]);
+    for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f((u2 * G::A + j) * 8u, B::posL(0, i) * 8u);
+    block_dft_tw<G::A, G::SR, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowi, M});
+#pragma unroll
+    for (int i = 0; i < B::E; ++i)
+        by.st32((uint32_t)to_i32(mulmod_var(v[i], tw4[i], M)), (u2 * G::A + j) * 4u, B::posL(0, i) * 4u);
 }
 
 // Kernels of the multi-launch four-step (grid.y = item / row of the batch).
 template <int LOGN>
 __global__ __launch_bounds__(256) void k_fs_col_fwd(const uint32_t* x, int32_t* Y, uint64_t item_stride,
                                                     uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FS<LOGN>::LDS];
-    col_fwd_block<LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p,
-                        lds);
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    col_fwd_block<LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
 }
 template <int LOGN>
 __global__ __launch_bounds__(256) void k_fs_row_conv(int32_t* Yf, const int32_t* Yg, uint64_t ystride,
                                                      DevPlan p) {
-    __shared__ double lds[FS<LOGN>::LDS];
-    row_conv_block<LOGN>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p,
-                         lds);
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    row_conv_block<LOGN>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
 }
 template <int LOGN, bool SCALE>
 __global__ __launch_bounds__(256) void k_fs_col_inv(const int32_t* Y, uint32_t* x, uint64_t item_stride,
                                                     uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FS<LOGN>::LDS];
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     col_inv_block<LOGN, SCALE>(Y + blockIdx.y * ystride, x + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SC,
-                               p, lds);
+                               p, L);
 }
 template <int LOGN>
 __global__ __launch_bounds__(256) void k_fs_row_fwd_nat(const int32_t* Y, uint32_t* X, uint64_t item_stride,
                                                         uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FS<LOGN>::LDS];
-    row_fwd_nat_block<LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SR, p,
-                            lds);
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    row_fwd_nat_block<LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SR, p, L);
 }
 template <int LOGN>
 __global__ __launch_bounds__(256) void k_fs_row_inv_nat(const uint32_t* X, int32_t* Y, uint64_t item_stride,
                                                         uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FS<LOGN>::LDS];
-    row_inv_nat_block<LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p,
-                            lds);
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    row_inv_nat_block<LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
 }
 
 // Persistent fused convolution of a uniform-length batch: one workgroup owns
@@ -278,17 +466,50 @@ __global__ __launch_bounds__(256) void k_conv_fused(const uint32_t* f, const uin
                                                     const uint64_t* __restrict__ offs, uint32_t count,
                                                     int32_t* scratch, DevPlan p) {
     using G = FS<LOGN>;
-    __shared__ double lds[G::LDS];
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     int32_t* Yf = scratch + (size_t)blockIdx.x * 2 * G::N;
     int32_t* Yg = Yf + G::N;
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
         const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
-        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<LOGN>(f + off, Yf, c0, p, lds);
-        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<LOGN>(g + off, Yg, c0, p, lds);
+        const uint32_t* fi = f + off;
+        const uint32_t* gi = g + off;
+        // columns of f then of g; the next block's loads are issued before
+        // the current block is transformed
+        constexpr int CL = G::A - G::SC;
+        ColIn<LOGN> cin = col_fwd_load<LOGN>(fi, 0);
+        for (int c0 = 0; c0 < CL; c0 += G::SC) {
+            const ColIn<LOGN> nxt = col_fwd_load<LOGN>(fi, c0 + G::SC);
+            col_fwd_compute<LOGN>(cin, Yf, c0, p, L);
+            cin = nxt;
+        }
+        {
+            const ColIn<LOGN> nxt = col_fwd_load<LOGN>(gi, 0);
+            col_fwd_compute<LOGN>(cin, Yf, CL, p, L);
+            cin = nxt;
+        }
+        for (int c0 = 0; c0 < CL; c0 += G::SC) {
+            const ColIn<LOGN> nxt = col_fwd_load<LOGN>(gi, c0 + G::SC);
+            col_fwd_compute<LOGN>(cin, Yg, c0, p, L);
+            cin = nxt;
+        }
+        col_fwd_compute<LOGN>(cin, Yg, CL, p, L);
         __syncthreads();
-        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<LOGN>(Yf, Yg, r0, p, lds);
+        RowIn<LOGN> rin = row_conv_load<LOGN>(Yf, Yg, 0);
+        for (int r0 = 0; r0 < G::Bn - G::SR; r0 += G::SR) {
+            const RowIn<LOGN> nxt = row_conv_load<LOGN>(Yf, Yg, r0 + G::SR);
+            row_conv_compute<LOGN>(rin, Yf, r0, p, L);
+            rin = nxt;
+        }
+        row_conv_compute<LOGN>(rin, Yf, G::Bn - G::SR, p, L);
         __syncthreads();
-        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_inv_block<LOGN, false>(Yf, h + off, c0, p, lds);
+        ColInvIn<LOGN> iin = col_inv_load<LOGN>(Yf, 0);
+        for (int c0 = 0; c0 < CL; c0 += G::SC) {
+            const ColInvIn<LOGN> nxt = col_inv_load<LOGN>(Yf, c0 + G::SC);
+            col_inv_compute<LOGN, false>(iin, h + off, c0, p, L);
+            iin = nxt;
+        }
+        col_inv_compute<LOGN, false>(iin, h + off, CL, p, L);
         __syncthreads();
     }
 }
@@ -313,7 +534,7 @@ hipError_t launch_range_check(const uint32_t* x, uint64_t n, uint32_t m, uint32_
 
 // ------------------------------------------------------------------ launchers
 #define NTT_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
-#define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+#define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
 
 hipError_t launch_conv_small(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, const uint64_t* offs,
                              uint32_t count, const DevPlan& p, hipStream_t st) {

@@ -10,15 +10,15 @@ namespace nttmi {
 // every kernel by value.
 struct DevPlan {
     const double2* P;    // P[e] = (w^e, w^e / m), e < N: powers of the N-th root
-    const double2* TT;   // four-step twiddles TT[u2 * A + t1] = w^(t1 u2) (large N only)
-    const double2* TTi;  // w^-(t1 u2)
+    const double* TT;    // four-step twiddles TT[u2 * A + t1] = w^(t1 u2) (large N only)
+    const double* TTi;   // w^-(t1 u2)
     ModC M;
     double ninv, ninvq;  // N^-1 mod m and N^-1 / m
     int logn, nmask;
 };
 
 constexpr int SMALL_MAX_LOG2N = 12;
-constexpr int MAX_LOG2N = 24;
+constexpr int MAX_LOG2N = 22;   // 32-bit words: m < 2^24, and no such prime has nu = 2^23
 
 hipError_t launch_conv_small(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, const uint64_t* offs,
                              uint32_t count, const DevPlan& p, hipStream_t st);
