@@ -102,8 +102,11 @@ template <int LOGN>
 struct FS {
     static constexpr int la = (LOGN + 1) / 2, lb = LOGN / 2;
     static constexpr int A = 1 << la, Bn = 1 << lb, N = 1 << LOGN;
-    static constexpr int SC = 4096 / Bn;   // columns per block (256 threads)
-    static constexpr int SR = 4096 / A;    // rows per block
+    // threads per workgroup: 512, so that a column block of B = 256 spans 32
+    // columns (128-byte rows of a block: whole cache lines)
+    static constexpr int T = 512;
+    static constexpr int SC = 16 * T / Bn; // columns per block
+    static constexpr int SR = 16 * T / A;  // rows per block
     using BC = Blk<Bn, SC, SEQ_FAST>;
     using BR = Blk<A, SR, POS_FAST>;
     using BRS = Blk<A, SR, SEQ_FAST>;      // rows read/written at stride B (natural-order NTT)
@@ -423,21 +426,21 @@ __device__ __forceinline__ void row_inv_nat_block(const uint32_t* X, int32_t* Y,
 
 // Kernels of the multi-launch four-step (grid.y = item / row of the batch).
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_fs_col_fwd(const uint32_t* x, int32_t* Y, uint64_t item_stride,
+__global__ __launch_bounds__(512) void k_fs_col_fwd(const uint32_t* x, int32_t* Y, uint64_t item_stride,
                                                     uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     col_fwd_block<LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
 }
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_fs_row_conv(int32_t* Yf, const int32_t* Yg, uint64_t ystride,
+__global__ __launch_bounds__(512) void k_fs_row_conv(int32_t* Yf, const int32_t* Yg, uint64_t ystride,
                                                      DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     row_conv_block<LOGN>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
 }
 template <int LOGN, bool SCALE>
-__global__ __launch_bounds__(256) void k_fs_col_inv(const int32_t* Y, uint32_t* x, uint64_t item_stride,
+__global__ __launch_bounds__(512) void k_fs_col_inv(const int32_t* Y, uint32_t* x, uint64_t item_stride,
                                                     uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
@@ -445,14 +448,14 @@ __global__ __launch_bounds__(256) void k_fs_col_inv(const int32_t* Y, uint32_t* 
                                p, L);
 }
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_fs_row_fwd_nat(const int32_t* Y, uint32_t* X, uint64_t item_stride,
+__global__ __launch_bounds__(512) void k_fs_row_fwd_nat(const int32_t* Y, uint32_t* X, uint64_t item_stride,
                                                         uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     row_fwd_nat_block<LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SR, p, L);
 }
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_fs_row_inv_nat(const uint32_t* X, int32_t* Y, uint64_t item_stride,
+__global__ __launch_bounds__(512) void k_fs_row_inv_nat(const uint32_t* X, int32_t* Y, uint64_t item_stride,
                                                         uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(256) void k_fs_row_inv_nat(const uint32_t* X, int32
 // Persistent fused convolution of a uniform-length batch: one workgroup owns
 // one convolution at a time, start to finish, with a private 2N-word scratch.
 template <int LOGN>
-__global__ __launch_bounds__(256) void k_conv_fused(const uint32_t* f, const uint32_t* g, uint32_t* h,
+__global__ __launch_bounds__(512) void k_conv_fused(const uint32_t* f, const uint32_t* g, uint32_t* h,
                                                     const uint64_t* __restrict__ offs, uint32_t count,
                                                     int32_t* scratch, DevPlan p) {
     using G = FS<LOGN>;
@@ -586,10 +589,10 @@ hipError_t launch_conv_fourstep(int logn, const uint32_t* f, const uint32_t* g, 
         const uint64_t ys = 2ull * G::N;                                                                      \
         int32_t* Yf = scratch;                                                                                \
         int32_t* Yg = scratch + G::N;                                                                         \
-        hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, items), dim3(256), 0, st, f, Yf, item_stride, ys, p); \
-        hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, items), dim3(256), 0, st, g, Yg, item_stride, ys, p); \
-        hipLaunchKernelGGL(k_fs_row_conv<n>, dim3(G::Bn / G::SR, items), dim3(256), 0, st, Yf, (const int32_t*)Yg, ys, p); \
-        hipLaunchKernelGGL((k_fs_col_inv<n, false>), dim3(G::A / G::SC, items), dim3(256), 0, st,           \
+        hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, items), dim3(G::T), 0, st, f, Yf, item_stride, ys, p); \
+        hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, items), dim3(G::T), 0, st, g, Yg, item_stride, ys, p); \
+        hipLaunchKernelGGL(k_fs_row_conv<n>, dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf, (const int32_t*)Yg, ys, p); \
+        hipLaunchKernelGGL((k_fs_col_inv<n, false>), dim3(G::A / G::SC, items), dim3(G::T), 0, st,           \
                            (const int32_t*)Yf, h, item_stride, ys, p);                                        \
         return hipGetLastError();                                                                             \
     }
@@ -609,12 +612,12 @@ hipError_t launch_ntt_fourstep(int logn, bool inv, const uint32_t* x, uint32_t* 
         using G = FS<n>;                                                                                      \
         const uint64_t N = G::N;                                                                              \
         if (!inv) {                                                                                           \
-            hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, batch), dim3(256), 0, st, x, scratch, N, N, p); \
-            hipLaunchKernelGGL(k_fs_row_fwd_nat<n>, dim3(G::Bn / G::SR, batch), dim3(256), 0, st,              \
+            hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, batch), dim3(G::T), 0, st, x, scratch, N, N, p); \
+            hipLaunchKernelGGL(k_fs_row_fwd_nat<n>, dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,              \
                                (const int32_t*)scratch, X, N, N, p);                                          \
         } else {                                                                                              \
-            hipLaunchKernelGGL(k_fs_row_inv_nat<n>, dim3(G::Bn / G::SR, batch), dim3(256), 0, st, x, scratch, N, N, p); \
-            hipLaunchKernelGGL((k_fs_col_inv<n, true>), dim3(G::A / G::SC, batch), dim3(256), 0, st,          \
+            hipLaunchKernelGGL(k_fs_row_inv_nat<n>, dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st, x, scratch, N, N, p); \
+            hipLaunchKernelGGL((k_fs_col_inv<n, true>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st,          \
                                (const int32_t*)scratch, X, N, N, p);                                          \
         }                                                                                                     \
         return hipGetLastError();                                                                             \
@@ -632,7 +635,7 @@ hipError_t launch_conv_fused(int logn, const uint32_t* f, const uint32_t* g, uin
     switch (logn) {
 #define CASE(n)                                                                                             \
     case n:                                                                                                 \
-        hipLaunchKernelGGL(k_conv_fused<n>, dim3(grid), dim3(256), 0, st, f, g, h, offs, count, scratch, p); \
+        hipLaunchKernelGGL(k_conv_fused<n>, dim3(grid), dim3(FS<n>::T), 0, st, f, g, h, offs, count, scratch, p); \
         return hipGetLastError();
         NTT_LARGE_CASES(CASE)
 #undef CASE
@@ -646,7 +649,7 @@ int fused_blocks_per_cu(int logn) {
     hipError_t e = hipErrorInvalidValue;
     switch (logn) {
 #define CASE(n) \
-    case n: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fused<n>, 256, 0); break;
+    case n: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fused<n>, FS<n>::T, 0); break;
         NTT_LARGE_CASES(CASE)
 #undef CASE
         default:
