@@ -54,7 +54,8 @@ ModC make_modc(uint64_t m) {
     M.m = (double)m;
     M.minv = 1.0 / (double)m;
     M.C = 6755399441055744.0;  // 1.5 * 2^52
-    M.Cm = M.C * (double)m;    // exact: 3m < 2^26
+    M.Cm = M.C * (double)m;    // exact for m < 2^26 (3m fits the significand)
+    M.c32 = (double)((1ull << 32) % m);
     return M;
 }
 
@@ -87,6 +88,8 @@ ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu) {
     if (*lnu < 0) return NTT_E_MODULUS;
     if (elem_bits == 32 && m >= (1ull << 24)) return NTT_E_MODULUS;
     if (elem_bits == 64 && m >= (1ull << 62)) return NTT_E_MODULUS;
+    // 64-bit words: residues are carried exactly in fp64, which holds m < 2^50
+    if (elem_bits == 64 && m >= (1ull << 50)) return NTT_E_UNSUPPORTED;
     return NTT_OK;
 }
 
@@ -102,7 +105,6 @@ ntt_status validate(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bit
     if (st != NTT_OK) return st;
     if ((int)log2n > *lnu) return NTT_E_LENGTH;
     if (!root_has_order(root, log2n, m)) return NTT_E_ROOT;
-    if (elem_bits == 64) return NTT_E_UNSUPPORTED;
     if (log2n > (uint32_t)MAX_LOG2N) return NTT_E_UNSUPPORTED;
     return NTT_OK;
 }
@@ -252,12 +254,12 @@ int overlap(const void* a, size_t na, const void* b, size_t nb) {
     return 2;
 }
 
-ntt_status check_range(const void* x, uint64_t n, uint64_t m, void* stream) {
+ntt_status check_range(uint32_t wbits, const void* x, uint64_t n, uint64_t m, void* stream) {
     void* flag = nullptr;
     ntt_status st = get_buf(caches().flag, stream, sizeof(uint32_t), &flag);
     if (st != NTT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_range_check((const uint32_t*)x, n, (uint32_t)m, (uint32_t*)flag, s);
+    hipError_t e = launch_range_check((int)wbits, x, n, m, (uint32_t*)flag, s);
     uint32_t hflag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -266,14 +268,15 @@ ntt_status check_range(const void* x, uint64_t n, uint64_t m, void* stream) {
 }
 
 // One convolution of length 2^log2n (plan already built) on the stream.
-ntt_status conv_one(const Plan* p, uint32_t log2n, const uint32_t* f, const uint32_t* g, uint32_t* h,
+ntt_status conv_one(const Plan* p, uint32_t wbits, uint32_t log2n, const void* f, const void* g, void* h,
                     void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if ((int)log2n <= SMALL_MAX_LOG2N) return hip_status(launch_conv_small(log2n, f, g, h, nullptr, 1, p->dev, s));
+    if ((int)log2n <= SMALL_MAX_LOG2N)
+        return hip_status(launch_conv_small((int)wbits, log2n, f, g, h, nullptr, 1, p->dev, s));
     void* ws = nullptr;
-    ntt_status st = get_buf(caches().work, stream, (size_t)2 * sizeof(int32_t) << log2n, &ws);
+    ntt_status st = get_buf(caches().work, stream, ((size_t)2 * (wbits / 8)) << log2n, &ws);
     if (st != NTT_OK) return st;
-    return hip_status(launch_conv_fourstep(log2n, f, g, h, 1, 0, (int32_t*)ws, p->dev, s));
+    return hip_status(launch_conv_fourstep((int)wbits, log2n, f, g, h, 1, 0, ws, p->dev, s));
 }
 
 ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* x, void* X,
@@ -286,7 +289,7 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
     const size_t bytes = ((size_t)batch << log2n) * (elem_bits / 8);
     if (overlap(x, bytes, X, bytes) == 2) return NTT_E_ARG;
     if (flags & NTT_FLAG_CHECK_RANGE) {
-        st = check_range(x, (uint64_t)batch << log2n, m, stream);
+        st = check_range(elem_bits, x, (uint64_t)batch << log2n, m, stream);
         if (st != NTT_OK) return st;
     }
     const Plan* p = nullptr;
@@ -294,12 +297,11 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
     if (st != NTT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if ((int)log2n <= SMALL_MAX_LOG2N)
-        return hip_status(launch_ntt_small(log2n, inv, (const uint32_t*)x, (uint32_t*)X, batch, p->dev, s));
+        return hip_status(launch_ntt_small((int)elem_bits, log2n, inv, x, X, batch, p->dev, s));
     void* ws = nullptr;
-    st = get_buf(caches().work, stream, ((size_t)batch * sizeof(int32_t)) << log2n, &ws);
+    st = get_buf(caches().work, stream, ((size_t)batch * (elem_bits / 8)) << log2n, &ws);
     if (st != NTT_OK) return st;
-    return hip_status(
-        launch_ntt_fourstep(log2n, inv, (const uint32_t*)x, (uint32_t*)X, batch, (int32_t*)ws, p->dev, s));
+    return hip_status(launch_ntt_fourstep((int)elem_bits, log2n, inv, x, X, batch, ws, p->dev, s));
 }
 
 }  // namespace
@@ -325,14 +327,14 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
     const size_t bytes = ((size_t)1 << log2n) * (elem_bits / 8);
     if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
     if (flags & NTT_FLAG_CHECK_RANGE) {
-        st = check_range(f, 1ull << log2n, m, stream);
-        if (st == NTT_OK) st = check_range(g, 1ull << log2n, m, stream);
+        st = check_range(elem_bits, f, 1ull << log2n, m, stream);
+        if (st == NTT_OK) st = check_range(elem_bits, g, 1ull << log2n, m, stream);
         if (st != NTT_OK) return st;
     }
     const Plan* p = nullptr;
     st = get_plan(m, log2n, root, lnu, &p);
     if (st != NTT_OK) return st;
-    return conv_one(p, log2n, (const uint32_t*)f, (const uint32_t*)g, (uint32_t*)h, stream);
+    return conv_one(p, elem_bits, log2n, f, g, h, stream);
 }
 
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
@@ -346,7 +348,6 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     if (!root_has_order(root, root_log2order, m)) return NTT_E_ROOT;
     if (d->count == 0) return NTT_OK;
     if (!d->log2n || !d->offset || !f || !g || !h) return NTT_E_ARG;
-    if (elem_bits == 64) return NTT_E_UNSUPPORTED;
     const uint32_t cnt = d->count;
     // items: lengths within the root's order, no two items overlapping
     std::vector<std::pair<uint64_t, uint64_t>> ext(cnt);
@@ -367,13 +368,14 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
     if (flags & NTT_FLAG_CHECK_RANGE) {
         // checks the whole extent, gaps between items included
-        st = check_range(f, total, m, stream);
-        if (st == NTT_OK) st = check_range(g, total, m, stream);
+        st = check_range(elem_bits, f, total, m, stream);
+        if (st == NTT_OK) st = check_range(elem_bits, g, total, m, stream);
         if (st != NTT_OK) return st;
     }
-    const uint32_t* F = (const uint32_t*)f;
-    const uint32_t* G = (const uint32_t*)g;
-    uint32_t* H = (uint32_t*)h;
+    const size_t wb = elem_bits / 8;   // bytes per word
+    const char* F = (const char*)f;
+    const char* G = (const char*)g;
+    char* H = (char*)h;
     hipStream_t s = (hipStream_t)stream;
 
     // length classes
@@ -389,7 +391,7 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
         if (st != NTT_OK) return st;
         if (flags & NTT_FLAG_PER_ITEM) {
             for (uint64_t o : off) {
-                st = conv_one(p, n, F + o, G + o, H + o, stream);
+                st = conv_one(p, elem_bits, n, F + o * wb, G + o * wb, H + o * wb, stream);
                 if (st != NTT_OK) return st;
             }
             continue;
@@ -405,25 +407,26 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
             if (st != NTT_OK) return st;
         }
         if ((int)n <= SMALL_MAX_LOG2N) {
-            st = hip_status(launch_conv_small(n, F + base, G + base, H + base, doffs, c, p->dev, s));
+            st = hip_status(
+                launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c, p->dev, s));
         } else {
             // persistent fused form: grid = resident workgroups, bounded by a
             // 1 GiB scratch budget (2N words per workgroup)
             // tuning override: NTTMI_FUSED_WG_PER_CU caps resident workgroups per CU
-            int per_cu = std::max(1, fused_blocks_per_cu(n));
+            int per_cu = std::max(1, fused_blocks_per_cu((int)elem_bits, n));
             if (const char* e = std::getenv("NTTMI_FUSED_WG_PER_CU")) {
                 const int cap = std::atoi(e);
                 if (cap > 0) per_cu = std::min(per_cu, cap);
             }
             uint64_t grid = (uint64_t)std::max(1, cus) * per_cu;
-            const uint64_t per_wg = (uint64_t)2 * sizeof(int32_t) << n;
+            const uint64_t per_wg = ((uint64_t)2 * wb) << n;
             grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));
             grid = std::min<uint64_t>(grid, c);
             void* ws = nullptr;
             st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
             if (st != NTT_OK) return st;
-            st = hip_status(launch_conv_fused(n, F + base, G + base, H + base, doffs, c, (int32_t*)ws,
-                                              (uint32_t)grid, p->dev, s));
+            st = hip_status(launch_conv_fused((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs,
+                                              c, ws, (uint32_t)grid, p->dev, s));
         }
         if (st != NTT_OK) return st;
     }

@@ -25,7 +25,8 @@ struct ModC {
     double m;      // the modulus
     double minv;   // fl(1/m)
     double C;      // 1.5 * 2^52 (round-to-integer shifter)
-    double Cm;     // C * m, exact because 3m < 2^26
+    double Cm;     // C * m (exact for 32-bit words: 3m < 2^26; unused for 64-bit words)
+    double c32;    // 2^32 mod m (64-bit words: reduction of the high half on load)
 };
 
 __device__ __forceinline__ double mulmod(double b, double w, double wq, const ModC& M) {
@@ -60,5 +61,79 @@ __device__ __forceinline__ uint32_t canon_u32(double y, const ModC& M) {
 // Scratch words hold reduced residues as signed 32-bit integers.
 __device__ __forceinline__ int32_t to_i32(double y) { return (int32_t)y; }
 __device__ __forceinline__ double from_i32(int32_t v) { return (double)v; }
+
+}  // namespace nttmi
+
+namespace nttmi {
+
+// ---------------------------------------------------------------------------
+// Word policies: how residues are loaded, multiplied and stored for each word
+// width.  Both carry residues as exact fp64 values.
+//
+// W32: 32-bit words, m < 2^24.  Twiddle products use the three-FMA form above
+//      with a precomputed w/m.  Scratch words are int32.
+// W64: 64-bit words, m < 2^50 (the 45-bit Rader prime of the serving
+//      workload).  A product b*w (up to ~2^94) is split exactly into
+//      hi = fl(b w) and lo = fma(b, w, -hi); the quotient q = round(hi/m) comes
+//      from an fp64 multiply; r = fma(-q, m, hi) + lo is exact because
+//      hi - q m is an integer below 2^53.  |r| <= 0.55 m for |b| <= 12 m.
+//      Scratch words are the fp64 values themselves.
+// ---------------------------------------------------------------------------
+struct W32 {
+    using word = uint32_t;
+    using sword = int32_t;
+    static constexpr int WB = 4;   // bytes per word
+    static constexpr int SB = 4;   // bytes per scratch word
+    __device__ static __forceinline__ double mul_tw(double b, const double2& w, const ModC& M) {
+        return mulmod(b, w.x, w.y, M);
+    }
+    __device__ static __forceinline__ double mul_w(double b, double w, const ModC& M) { return mulmod_var(b, w, M); }
+    __device__ static __forceinline__ double mul_var(double a, double b, const ModC& M) { return mulmod_var(a, b, M); }
+    __device__ static __forceinline__ double load_reduce(word x, const ModC& M) { return reduce((double)x, M); }
+    __device__ static __forceinline__ word canon(double y, const ModC& M) { return canon_u32(y, M); }
+    __device__ static __forceinline__ sword to_s(double y) { return (int32_t)y; }
+    __device__ static __forceinline__ double from_s(sword v) { return (double)v; }
+};
+
+__device__ __forceinline__ double mulmod_dd(double b, double w, const ModC& M) {
+    const double hi = b * w;
+    const double lo = __builtin_fma(b, w, -hi);
+    const double q = __builtin_fma(hi, M.minv, M.C) - M.C;
+    const double r1 = __builtin_fma(q, -M.m, hi);
+    return r1 + lo;
+}
+
+// y mod m into about [-m/2, m/2] for |y| < 2^52 (64-bit words).
+__device__ __forceinline__ double reduce_dd(double y, const ModC& M) {
+    const double q = __builtin_fma(y, M.minv, M.C) - M.C;
+    return __builtin_fma(q, -M.m, y);
+}
+
+struct W64 {
+    using word = uint64_t;
+    using sword = double;
+    static constexpr int WB = 8;
+    static constexpr int SB = 8;
+    __device__ static __forceinline__ double mul_tw(double b, const double2& w, const ModC& M) {
+        return mulmod_dd(b, w.x, M);
+    }
+    __device__ static __forceinline__ double mul_w(double b, double w, const ModC& M) { return mulmod_dd(b, w, M); }
+    __device__ static __forceinline__ double mul_var(double a, double b, const ModC& M) { return mulmod_dd(a, b, M); }
+    // x = xh 2^32 + xl; (xh * (2^32 mod m) mod m) + xl, then reduced
+    __device__ static __forceinline__ double load_reduce(word x, const ModC& M) {
+        const double h = mulmod_dd((double)(uint32_t)(x >> 32), M.c32, M);
+        return reduce_dd(h + (double)(uint32_t)x, M);
+    }
+    __device__ static __forceinline__ word canon(double y, const ModC& M) {
+        double r = reduce_dd(y, M);
+        r = (r < 0.0) ? r + M.m : r;
+        r = (r >= M.m) ? r - M.m : r;
+        const double hi = __builtin_floor(r * 2.3283064365386963e-10);   // 2^-32
+        const double lo = __builtin_fma(hi, -4294967296.0, r);
+        return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+    }
+    __device__ static __forceinline__ sword to_s(double y) { return y; }
+    __device__ static __forceinline__ double from_s(sword v) { return v; }
+};
 
 }  // namespace nttmi

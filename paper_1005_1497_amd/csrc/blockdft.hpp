@@ -33,7 +33,7 @@ constexpr int brevc(int i, int bits) {
 //   a[o] <- sum_i a[i] w_R^(i o).
 // Radix-2 decimation in time on bit-reversed registers.  tw[e * ts] = w_R^e
 // for e < R/2 as (w, w/m).
-template <int R>
+template <class W, int R>
 __device__ __forceinline__ void dft_reg(double* a, const double2* tw, int ts, const ModC& M) {
     constexpr int LB = ilog2c(R);
     double t[R];
@@ -48,8 +48,7 @@ __device__ __forceinline__ void dft_reg(double* a, const double2* tw, int ts, co
                 double x = t[g + k];
                 double y = t[g + k + span];
                 if (k != 0) {
-                    const double2 w = tw[k * (R / (2 * span)) * ts];
-                    y = mulmod(y, w.x, w.y, M);
+                    y = W::mul_tw(y, tw[k * (R / (2 * span)) * ts], M);
                 }
                 t[g + k] = x + y;
                 t[g + k + span] = x - y;
@@ -111,7 +110,7 @@ struct Blk {
 // v[r] *= tw(r) mod m for r < R, with the table loads software-pipelined in
 // groups of four (at most eight 16-byte twiddles in flight per lane), so that
 // the loads do not all sit in VGPRs at once.
-template <int R, class TW>
+template <class W, int R, class TW>
 __device__ __forceinline__ void mul_twiddles(double* v, const ModC& M, TW tw) {
     constexpr int G = R < 4 ? R : 4;
     double2 w0[G], w1[G];
@@ -125,7 +124,7 @@ __device__ __forceinline__ void mul_twiddles(double* v, const ModC& M, TW tw) {
             for (int q = 0; q < G; ++q) w1[q] = tw((g + 1) * G + q);
         }
 #pragma unroll
-        for (int q = 0; q < G; ++q) v[g * G + q] = mulmod(v[g * G + q], w0[q].x, w0[q].y, M);
+        for (int q = 0; q < G; ++q) v[g * G + q] = W::mul_tw(v[g * G + q], w0[q], M);
 #pragma unroll
         for (int q = 0; q < G; ++q) w0[q] = w1[q];
     }
@@ -146,7 +145,7 @@ __device__ __forceinline__ int tw_index(int eL, int lshift, int nmask) {
 // at position Blk::pos0(j, i) of sequence s (reduced); on exit v[i] holds the
 // output at Blk::posL(j, i).  `ldsbuf` must be free on entry and is free on
 // exit.  P is the power table of the item's N-th root (N = L << lshift).
-template <int L, int S, int ORD, bool INV, class TWF>
+template <class W, int L, int S, int ORD, bool INV, class TWF>
 __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, int j,
                                              const double2* __restrict__ P, int lshift, int nmask,
                                              const ModC& M, TWF twf) {
@@ -161,7 +160,7 @@ __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, i
 
     // pass 0: V0 independent DFTs of radix R0, no inter-pass twiddle
 #pragma unroll
-    for (int vv = 0; vv < B::V0; ++vv) dft_reg<B::R0>(v + vv * B::R0, twE, E / B::R0, M);
+    for (int vv = 0; vv < B::V0; ++vv) dft_reg<W, B::R0>(v + vv * B::R0, twE, E / B::R0, M);
 
     int Ns = B::R0;
 #pragma unroll
@@ -185,7 +184,7 @@ __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, i
         __syncthreads();
         // inter-pass twiddles w_{16 Ns}^(r k) = w_L^((L/(16 Ns)) r k), k = j mod Ns
         twf(v, p, Ns, j & (Ns - 1));
-        dft_reg<16>(v, twE, 1, M);
+        dft_reg<W, 16>(v, twE, 1, M);
         Ns *= 16;
     }
 }
@@ -207,13 +206,13 @@ struct PassTab {
 
 // block_dft_tw with the inter-pass twiddles read from the global power table
 // (software-pipelined loads).
-template <int L, int S, int ORD, bool INV>
+template <class W, int L, int S, int ORD, bool INV>
 __device__ __forceinline__ void block_dft(double* v, double* ldsbuf, int s, int j,
                                           const double2* __restrict__ P, int lshift, int nmask,
                                           const ModC& M) {
-    block_dft_tw<L, S, ORD, INV>(v, ldsbuf, s, j, P, lshift, nmask, M, [&](double* vv, int, int Ns, int k) {
+    block_dft_tw<W, L, S, ORD, INV>(v, ldsbuf, s, j, P, lshift, nmask, M, [&](double* vv, int, int Ns, int k) {
         const int step = (L / (16 * Ns)) * k;
-        mul_twiddles<16>(vv, M, [&](int r) { return P[tw_index<INV>(step * r, lshift, nmask)]; });
+        mul_twiddles<W, 16>(vv, M, [&](int r) { return P[tw_index<INV>(step * r, lshift, nmask)]; });
     });
 }
 

@@ -24,10 +24,10 @@ namespace nttmi {
 // ------------------------------------------------------------------ small N
 constexpr int small_s(int L) { return L < 16 ? 256 : 4096 / L; }
 
-template <int L>
-__global__ __launch_bounds__(256) void k_conv_small(const uint32_t* f, const uint32_t* g, uint32_t* h,
-                                                    const uint64_t* __restrict__ offs, uint32_t count,
-                                                    DevPlan p) {
+template <class W, int L>
+__global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, const typename W::word* g,
+                                                    typename W::word* h, const uint64_t* __restrict__ offs,
+                                                    uint32_t count, DevPlan p) {
     constexpr int S = small_s(L);
     using B = Blk<L, S, POS_FAST>;
     __shared__ double lds[B::LDS_DOUBLES];
@@ -40,18 +40,18 @@ __global__ __launch_bounds__(256) void k_conv_small(const uint32_t* f, const uin
     const int lshift = p.logn - B::l;
     double F[B::E], v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)f[off + B::pos0(j, i)], M);
-    block_dft<L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
+    for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(f[off + B::pos0(j, i)], M);
+    block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) F[i] = v[i];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)g[off + B::pos0(j, i)], M);
-    block_dft<L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
+    for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(g[off + B::pos0(j, i)], M);
+    block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
     // pointwise product with N^-1 folded in: F * (G * N^-1)
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
-        const double gs = mulmod(v[i], p.ninv, p.ninvq, M);
-        v[i] = mulmod_var(F[i], gs, M);
+        const double gs = W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M);
+        v[i] = W::mul_var(F[i], gs, M);
     }
     if (B::R0 != B::RL) {
         // output positions of the forward transform differ from the input
@@ -63,15 +63,16 @@ __global__ __launch_bounds__(256) void k_conv_small(const uint32_t* f, const uin
         for (int i = 0; i < B::E; ++i) v[i] = lds[B::lds(s, B::pos0(j, i))];
         __syncthreads();
     }
-    block_dft<L, S, POS_FAST, true>(v, lds, s, j, p.P, lshift, p.nmask, M);
+    block_dft<W, L, S, POS_FAST, true>(v, lds, s, j, p.P, lshift, p.nmask, M);
     if (valid) {
 #pragma unroll
-        for (int i = 0; i < B::E; ++i) h[off + B::posL(j, i)] = canon_u32(v[i], M);
+        for (int i = 0; i < B::E; ++i) h[off + B::posL(j, i)] = W::canon(v[i], M);
     }
 }
 
-template <int L, bool INV>
-__global__ __launch_bounds__(256) void k_ntt_small(const uint32_t* x, uint32_t* X, uint32_t batch, DevPlan p) {
+template <class W, int L, bool INV>
+__global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, typename W::word* X, uint32_t batch,
+                                                   DevPlan p) {
     constexpr int S = small_s(L);
     using B = Blk<L, S, POS_FAST>;
     __shared__ double lds[B::LDS_DOUBLES];
@@ -83,13 +84,13 @@ __global__ __launch_bounds__(256) void k_ntt_small(const uint32_t* x, uint32_t* 
     const ModC M = p.M;
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)x[off + B::pos0(j, i)], M);
-    block_dft<L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M);
+    for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(x[off + B::pos0(j, i)], M);
+    block_dft<W, L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M);
     if (valid) {
 #pragma unroll
         for (int i = 0; i < B::E; ++i) {
-            const double y = INV ? mulmod(v[i], p.ninv, p.ninvq, M) : v[i];
-            X[off + B::posL(j, i)] = canon_u32(y, M);
+            const double y = INV ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
+            X[off + B::posL(j, i)] = W::canon(y, M);
         }
     }
 }
@@ -134,7 +135,41 @@ struct Buf {
     __device__ __forceinline__ void st32(uint32_t x, uint32_t v, uint32_t s) const {
         __builtin_amdgcn_raw_buffer_store_b32(x, r, v, s, 0);
     }
+    __device__ __forceinline__ uint64_t ld64(uint32_t v, uint32_t s) const {
+        return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    __device__ __forceinline__ void st64(uint64_t x, uint32_t v, uint32_t s) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, x),
+                                              r, v, s, 0);
+    }
 };
+
+// Word and scratch accesses by element offsets (per-lane, uniform).
+template <class W>
+__device__ __forceinline__ typename W::word ld_word(const Buf& b, uint32_t ve, uint32_t se) {
+    if constexpr (W::WB == 4) return b.ld32(ve * 4u, se * 4u);
+    else return b.ld64(ve * 8u, se * 8u);
+}
+template <class W>
+__device__ __forceinline__ void st_word(const Buf& b, typename W::word x, uint32_t ve, uint32_t se) {
+    if constexpr (W::WB == 4) b.st32(x, ve * 4u, se * 4u);
+    else b.st64(x, ve * 8u, se * 8u);
+}
+template <class W>
+__device__ __forceinline__ double ld_scr(const Buf& b, uint32_t ve, uint32_t se) {
+    if constexpr (W::SB == 4) return W::from_s(b.ldi32(ve * 4u, se * 4u));
+    else return b.ld64f(ve * 8u, se * 8u);
+}
+template <class W>
+__device__ __forceinline__ typename W::sword ld_scr_raw(const Buf& b, uint32_t ve, uint32_t se) {
+    if constexpr (W::SB == 4) return b.ldi32(ve * 4u, se * 4u);
+    else return b.ld64f(ve * 8u, se * 8u);
+}
+template <class W>
+__device__ __forceinline__ void st_scr(const Buf& b, double y, uint32_t ve, uint32_t se) {
+    if constexpr (W::SB == 4) b.st32((uint32_t)W::to_s(y), ve * 4u, se * 4u);
+    else b.st64(__builtin_bit_cast(uint64_t, y), ve * 8u, se * 8u);
+}
 
 // Shared-memory layout of a four-step workgroup: the pass exchange buffer and
 // the per-pass twiddle tables of the column (length B) and row (length A)
@@ -195,14 +230,14 @@ __device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p
 }
 
 // Inter-pass twiddles of a length-L transform from its shared pass table.
-template <int L>
+template <class W, int L>
 struct TwTab {
     const double* t;
     ModC M;
     __device__ __forceinline__ void operator()(double* v, int p, int, int k) const {
         const double* b = t + PassTab<L>::off(p) + PassTab<L>::ROW * k;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = mulmod_var(v[r], b[r], M);
+        for (int r = 0; r < 16; ++r) v[r] = W::mul_w(v[r], b[r], M);
     }
 };
 
@@ -210,106 +245,109 @@ struct TwTab {
 // (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
 // Positions of a work item are j + const(i), so every access is a buffer
 // access with one per-lane offset and a compile-time uniform offset.
-template <int LOGN>
+template <class W, int LOGN>
 struct ColIn {
-    uint32_t w[FS<LOGN>::BC::E];
+    typename W::word w[FS<LOGN>::BC::E];
 };
 
 // Raw loads of a forward column block (issued ahead of its transform).
-template <int LOGN>
-__device__ __forceinline__ ColIn<LOGN> col_fwd_load(const uint32_t* x, int c0) {
+// Positions of a work item are j + const(i), so every access is a buffer
+// access with one per-lane offset and a compile-time uniform offset.
+template <class W, int LOGN>
+__device__ __forceinline__ ColIn<W, LOGN> col_fwd_load(const typename W::word* x, int c0) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
-    const Buf bx(x, G::N * 4u);
-    ColIn<LOGN> in;
+    const Buf bx(x, G::N * W::WB);
+    ColIn<W, LOGN> in;
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) in.w[i] = bx.ld32((c0 + s + G::A * j) * 4u, G::A * (B::pos0(0, i)) * 4u);
+    for (int i = 0; i < B::E; ++i) in.w[i] = ld_word<W>(bx, c0 + s + G::A * j, G::A * B::pos0(0, i));
     return in;
 }
 
-template <int LOGN>
-__device__ __forceinline__ void col_fwd_compute(const ColIn<LOGN>& in, int32_t* Y, int c0, const DevPlan& p,
-                                                const FSLds<LOGN>& L) {
+// Column phase, forward: length-B transforms of columns c0..c0+SC of x
+// (natural order), times w^(t1 u2), into scratch rows Y[u2 * A + t1].
+template <class W, int LOGN>
+__device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typename W::sword* Y, int c0,
+                                                const DevPlan& p, const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int t1 = c0 + s;
-    const Buf by(Y, G::N * 4u), bt(p.TT, G::N * 8u);
+    const Buf by(Y, G::N * W::SB), bt(p.TT, G::N * 8u);
     double v[B::E];
     // four-step twiddles, loaded ahead of the transform
     double tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f((j * G::A + t1) * 8u, B::posL(0, i) * G::A * 8u);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)in.w[i], M);
-    block_dft_tw<G::Bn, G::SC, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::la, G::N - 1, M, TwTab<G::Bn>{L.colf, M});
+    for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(in.w[i], M);
+    block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
+                                                   TwTab<W, G::Bn>{L.colf, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i)
-        by.st32((uint32_t)to_i32(mulmod_var(v[i], tw4[i], M)), (j * G::A + t1) * 4u, B::posL(0, i) * G::A * 4u);
+    for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], tw4[i], M), j * G::A + t1, B::posL(0, i) * G::A);
 }
 
-// Column phase, forward: length-B transforms of columns c0..c0+SC of x
-// (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
-// Positions of a work item are j + const(i), so every access is a buffer
-// access with one per-lane offset and a compile-time uniform offset.
-template <int LOGN>
-__device__ __forceinline__ void col_fwd_block(const uint32_t* x, int32_t* Y, int c0, const DevPlan& p,
-                                              const FSLds<LOGN>& L) {
-    col_fwd_compute<LOGN>(col_fwd_load<LOGN>(x, c0), Y, c0, p, L);
+template <class W, int LOGN>
+__device__ __forceinline__ void col_fwd_block(const typename W::word* x, typename W::sword* Y, int c0,
+                                              const DevPlan& p, const FSLds<LOGN>& L) {
+    col_fwd_compute<W, LOGN>(col_fwd_load<W, LOGN>(x, c0), Y, c0, p, L);
 }
 
 // Row phase of a convolution: for rows r0..r0+SR, forward(f row), forward(g
 // row), product with N^-1, inverse, times w^-(t1 u2), back into Yf.
-template <int LOGN>
+template <class W, int LOGN>
 struct RowIn {
-    int32_t f[FS<LOGN>::BR::E];
-    int32_t g[FS<LOGN>::BR::E];
+    typename W::sword f[FS<LOGN>::BR::E];
+    typename W::sword g[FS<LOGN>::BR::E];
 };
 
-template <int LOGN>
-__device__ __forceinline__ RowIn<LOGN> row_conv_load(const int32_t* Yf, const int32_t* Yg, int r0) {
+template <class W, int LOGN>
+__device__ __forceinline__ RowIn<W, LOGN> row_conv_load(const typename W::sword* Yf, const typename W::sword* Yg,
+                                                        int r0) {
     using G = FS<LOGN>;
     using B = typename G::BR;
     int s, j;
     B::item(threadIdx.x, s, j);
-    const Buf bf(Yf, G::N * 4u), bg(Yg, G::N * 4u);
+    const Buf bf(Yf, G::N * W::SB), bg(Yg, G::N * W::SB);
     const uint32_t rowoff = (uint32_t)((r0 + s) * G::A + j);
-    RowIn<LOGN> in;
+    RowIn<W, LOGN> in;
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) in.f[i] = bf.ldi32(rowoff * 4u, B::pos0(0, i) * 4u);
+    for (int i = 0; i < B::E; ++i) in.f[i] = ld_scr_raw<W>(bf, rowoff, B::pos0(0, i));
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) in.g[i] = bg.ldi32(rowoff * 4u, B::pos0(0, i) * 4u);
+    for (int i = 0; i < B::E; ++i) in.g[i] = ld_scr_raw<W>(bg, rowoff, B::pos0(0, i));
     return in;
 }
 
-template <int LOGN>
-__device__ __forceinline__ void row_conv_compute(const RowIn<LOGN>& in, int32_t* Yf, int r0, const DevPlan& p,
-                                                 const FSLds<LOGN>& L) {
+template <class W, int LOGN>
+__device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typename W::sword* Yf, int r0,
+                                                 const DevPlan& p, const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BR;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf bf(Yf, G::N * 4u), bt(p.TTi, G::N * 8u);
+    const Buf bf(Yf, G::N * W::SB), bt(p.TTi, G::N * 8u);
     const uint32_t rowoff = (uint32_t)(u2 * G::A + j);
     double F[B::E], v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(in.f[i]);
-    block_dft_tw<G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowf, M});
+    for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.f[i]);
+    block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                  TwTab<W, G::A>{L.rowf, M});
 #pragma unroll
     for (int i = 0; i < B::E; ++i) F[i] = v[i];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(in.g[i]);
-    block_dft_tw<G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowf, M});
+    for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.g[i]);
+    block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                  TwTab<W, G::A>{L.rowf, M});
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
-        const double gs = mulmod(v[i], p.ninv, p.ninvq, M);
-        v[i] = mulmod_var(F[i], gs, M);
+        const double gs = W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M);
+        v[i] = W::mul_var(F[i], gs, M);
     }
     if (B::R0 != B::RL) {
 #pragma unroll
@@ -322,216 +360,226 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<LOGN>& in, int32_t*
     double tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f(rowoff * 8u, B::posL(0, i) * 8u);
-    block_dft_tw<G::A, G::SR, POS_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowi, M});
+    block_dft_tw<W, G::A, G::SR, POS_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                 TwTab<W, G::A>{L.rowi, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i)
-        bf.st32((uint32_t)to_i32(mulmod_var(v[i], tw4[i], M)), rowoff * 4u, B::posL(0, i) * 4u);
+    for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], tw4[i], M), rowoff, B::posL(0, i));
 }
 
-template <int LOGN>
-__device__ __forceinline__ void row_conv_block(int32_t* Yf, const int32_t* Yg, int r0, const DevPlan& p,
-                                               const FSLds<LOGN>& L) {
-    row_conv_compute<LOGN>(row_conv_load<LOGN>(Yf, Yg, r0), Yf, r0, p, L);
+template <class W, int LOGN>
+__device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const typename W::sword* Yg, int r0,
+                                               const DevPlan& p, const FSLds<LOGN>& L) {
+    row_conv_compute<W, LOGN>(row_conv_load<W, LOGN>(Yf, Yg, r0), Yf, r0, p, L);
 }
 
 // Column phase, inverse: length-B inverse transforms of scratch columns,
 // optional N^-1, canonical store to x[t1 + A t2].
-template <int LOGN>
+template <class W, int LOGN>
 struct ColInvIn {
-    int32_t w[FS<LOGN>::BC::E];
+    typename W::sword w[FS<LOGN>::BC::E];
 };
 
-template <int LOGN>
-__device__ __forceinline__ ColInvIn<LOGN> col_inv_load(const int32_t* Y, int c0) {
+template <class W, int LOGN>
+__device__ __forceinline__ ColInvIn<W, LOGN> col_inv_load(const typename W::sword* Y, int c0) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
-    const Buf by(Y, G::N * 4u);
-    ColInvIn<LOGN> in;
+    const Buf by(Y, G::N * W::SB);
+    ColInvIn<W, LOGN> in;
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) in.w[i] = by.ldi32((j * G::A + c0 + s) * 4u, B::pos0(0, i) * G::A * 4u);
+    for (int i = 0; i < B::E; ++i) in.w[i] = ld_scr_raw<W>(by, j * G::A + c0 + s, B::pos0(0, i) * G::A);
     return in;
 }
 
-template <int LOGN, bool SCALE>
-__device__ __forceinline__ void col_inv_compute(const ColInvIn<LOGN>& in, uint32_t* x, int c0, const DevPlan& p,
-                                                const FSLds<LOGN>& L) {
+template <class W, int LOGN, bool SCALE>
+__device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typename W::word* x, int c0,
+                                                const DevPlan& p, const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
-    const Buf bx(x, G::N * 4u);
+    const Buf bx(x, G::N * W::WB);
     const uint32_t off = (uint32_t)(j * G::A + c0 + s);
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(in.w[i]);
-    block_dft_tw<G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M, TwTab<G::Bn>{L.coli, M});
+    for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.w[i]);
+    block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
+                                                  TwTab<W, G::Bn>{L.coli, M});
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
-        const double y = SCALE ? mulmod(v[i], p.ninv, p.ninvq, M) : v[i];
-        bx.st32(canon_u32(y, M), off * 4u, B::posL(0, i) * G::A * 4u);
+        const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
+        st_word<W>(bx, W::canon(y, M), off, B::posL(0, i) * G::A);
     }
 }
 
-template <int LOGN, bool SCALE>
-__device__ __forceinline__ void col_inv_block(const int32_t* Y, uint32_t* x, int c0, const DevPlan& p,
-                                              const FSLds<LOGN>& L) {
-    col_inv_compute<LOGN, SCALE>(col_inv_load<LOGN>(Y, c0), x, c0, p, L);
+template <class W, int LOGN, bool SCALE>
+__device__ __forceinline__ void col_inv_block(const typename W::sword* Y, typename W::word* x, int c0,
+                                              const DevPlan& p, const FSLds<LOGN>& L) {
+    col_inv_compute<W, LOGN, SCALE>(col_inv_load<W, LOGN>(Y, c0), x, c0, p, L);
 }
 
 // Row phase of the natural-order forward transform: X[u2 + B u1].
-template <int LOGN>
-__device__ __forceinline__ void row_fwd_nat_block(const int32_t* Y, uint32_t* X, int r0, const DevPlan& p,
-                                                  const FSLds<LOGN>& L) {
+template <class W, int LOGN>
+__device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, typename W::word* X, int r0,
+                                                  const DevPlan& p, const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BRS;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf by(Y, G::N * 4u), bx(X, G::N * 4u);
+    const Buf by(Y, G::N * W::SB), bx(X, G::N * W::WB);
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = from_i32(by.ldi32((u2 * G::A + j) * 4u, B::pos0(0, i) * 4u));
-    block_dft_tw<G::A, G::SR, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowf, M});
+    for (int i = 0; i < B::E; ++i) v[i] = ld_scr<W>(by, u2 * G::A + j, B::pos0(0, i));
+    block_dft_tw<W, G::A, G::SR, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                  TwTab<W, G::A>{L.rowf, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) bx.st32(canon_u32(v[i], M), (u2 + G::Bn * j) * 4u, G::Bn * B::posL(0, i) * 4u);
+    for (int i = 0; i < B::E; ++i) st_word<W>(bx, W::canon(v[i], M), u2 + G::Bn * j, G::Bn * B::posL(0, i));
 }
 
 // Row phase of the natural-order inverse transform: from X[u2 + B u1] to
 // scratch rows, times w^-(t1 u2).
-template <int LOGN>
-__device__ __forceinline__ void row_inv_nat_block(const uint32_t* X, int32_t* Y, int r0, const DevPlan& p,
-                                                  const FSLds<LOGN>& L) {
+template <class W, int LOGN>
+__device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typename W::sword* Y, int r0,
+                                                  const DevPlan& p, const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
     using B = typename G::BRS;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf bx(X, G::N * 4u), by(Y, G::N * 4u), bt(p.TTi, G::N * 8u);
+    const Buf bx(X, G::N * W::WB), by(Y, G::N * W::SB), bt(p.TTi, G::N * 8u);
     double v[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = reduce((double)bx.ld32((u2 + G::Bn * j) * 4u, G::Bn * B::pos0(0, i) * 4u), M);
+    for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(ld_word<W>(bx, u2 + G::Bn * j, G::Bn * B::pos0(0, i)), M);
     double tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f((u2 * G::A + j) * 8u, B::posL(0, i) * 8u);
-    block_dft_tw<G::A, G::SR, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M, TwTab<G::A>{L.rowi, M});
+    block_dft_tw<W, G::A, G::SR, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                 TwTab<W, G::A>{L.rowi, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i)
-        by.st32((uint32_t)to_i32(mulmod_var(v[i], tw4[i], M)), (u2 * G::A + j) * 4u, B::posL(0, i) * 4u);
+    for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], tw4[i], M), u2 * G::A + j, B::posL(0, i));
 }
 
 // Kernels of the multi-launch four-step (grid.y = item / row of the batch).
-template <int LOGN>
-__global__ __launch_bounds__(512) void k_fs_col_fwd(const uint32_t* x, int32_t* Y, uint64_t item_stride,
-                                                    uint64_t ystride, DevPlan p) {
+template <class W, int LOGN>
+__global__ __launch_bounds__(512) void k_fs_col_fwd(const typename W::word* x, typename W::sword* Y,
+                                                    uint64_t item_stride, uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    col_fwd_block<LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
+    col_fwd_block<W, LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
 }
-template <int LOGN>
-__global__ __launch_bounds__(512) void k_fs_row_conv(int32_t* Yf, const int32_t* Yg, uint64_t ystride,
-                                                     DevPlan p) {
+template <class W, int LOGN>
+__global__ __launch_bounds__(512) void k_fs_row_conv(typename W::sword* Yf, const typename W::sword* Yg,
+                                                     uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    row_conv_block<LOGN>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
+    row_conv_block<W, LOGN>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
 }
-template <int LOGN, bool SCALE>
-__global__ __launch_bounds__(512) void k_fs_col_inv(const int32_t* Y, uint32_t* x, uint64_t item_stride,
-                                                    uint64_t ystride, DevPlan p) {
+template <class W, int LOGN, bool SCALE>
+__global__ __launch_bounds__(512) void k_fs_col_inv(const typename W::sword* Y, typename W::word* x,
+                                                    uint64_t item_stride, uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    col_inv_block<LOGN, SCALE>(Y + blockIdx.y * ystride, x + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SC,
-                               p, L);
+    col_inv_block<W, LOGN, SCALE>(Y + blockIdx.y * ystride, x + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SC,
+                                  p, L);
 }
-template <int LOGN>
-__global__ __launch_bounds__(512) void k_fs_row_fwd_nat(const int32_t* Y, uint32_t* X, uint64_t item_stride,
-                                                        uint64_t ystride, DevPlan p) {
+template <class W, int LOGN>
+__global__ __launch_bounds__(512) void k_fs_row_fwd_nat(const typename W::sword* Y, typename W::word* X,
+                                                        uint64_t item_stride, uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    row_fwd_nat_block<LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SR, p, L);
+    row_fwd_nat_block<W, LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SR, p,
+                               L);
 }
-template <int LOGN>
-__global__ __launch_bounds__(512) void k_fs_row_inv_nat(const uint32_t* X, int32_t* Y, uint64_t item_stride,
-                                                        uint64_t ystride, DevPlan p) {
+template <class W, int LOGN>
+__global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* X, typename W::sword* Y,
+                                                        uint64_t item_stride, uint64_t ystride, DevPlan p) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    row_inv_nat_block<LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
+    row_inv_nat_block<W, LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p,
+                               L);
 }
 
 // Persistent fused convolution of a uniform-length batch: one workgroup owns
 // one convolution at a time, start to finish, with a private 2N-word scratch.
-template <int LOGN>
-__global__ __launch_bounds__(512) void k_conv_fused(const uint32_t* f, const uint32_t* g, uint32_t* h,
-                                                    const uint64_t* __restrict__ offs, uint32_t count,
-                                                    int32_t* scratch, DevPlan p) {
+template <class W, int LOGN>
+__global__ __launch_bounds__(512) void k_conv_fused(const typename W::word* f, const typename W::word* g,
+                                                    typename W::word* h, const uint64_t* __restrict__ offs,
+                                                    uint32_t count, typename W::sword* scratch, DevPlan p) {
     using G = FS<LOGN>;
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    int32_t* Yf = scratch + (size_t)blockIdx.x * 2 * G::N;
-    int32_t* Yg = Yf + G::N;
+    typename W::sword* Yf = scratch + (size_t)blockIdx.x * 2 * G::N;
+    typename W::sword* Yg = Yf + G::N;
+    constexpr int CL = G::A - G::SC;
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
         const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
-        const uint32_t* fi = f + off;
-        const uint32_t* gi = g + off;
+        const typename W::word* fi = f + off;
+        const typename W::word* gi = g + off;
         // columns of f then of g; the next block's loads are issued before
         // the current block is transformed
-        constexpr int CL = G::A - G::SC;
-        ColIn<LOGN> cin = col_fwd_load<LOGN>(fi, 0);
+        ColIn<W, LOGN> cin = col_fwd_load<W, LOGN>(fi, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
-            const ColIn<LOGN> nxt = col_fwd_load<LOGN>(fi, c0 + G::SC);
-            col_fwd_compute<LOGN>(cin, Yf, c0, p, L);
+            const ColIn<W, LOGN> nxt = col_fwd_load<W, LOGN>(fi, c0 + G::SC);
+            col_fwd_compute<W, LOGN>(cin, Yf, c0, p, L);
             cin = nxt;
         }
         {
-            const ColIn<LOGN> nxt = col_fwd_load<LOGN>(gi, 0);
-            col_fwd_compute<LOGN>(cin, Yf, CL, p, L);
+            const ColIn<W, LOGN> nxt = col_fwd_load<W, LOGN>(gi, 0);
+            col_fwd_compute<W, LOGN>(cin, Yf, CL, p, L);
             cin = nxt;
         }
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
-            const ColIn<LOGN> nxt = col_fwd_load<LOGN>(gi, c0 + G::SC);
-            col_fwd_compute<LOGN>(cin, Yg, c0, p, L);
+            const ColIn<W, LOGN> nxt = col_fwd_load<W, LOGN>(gi, c0 + G::SC);
+            col_fwd_compute<W, LOGN>(cin, Yg, c0, p, L);
             cin = nxt;
         }
-        col_fwd_compute<LOGN>(cin, Yg, CL, p, L);
+        col_fwd_compute<W, LOGN>(cin, Yg, CL, p, L);
         __syncthreads();
-        RowIn<LOGN> rin = row_conv_load<LOGN>(Yf, Yg, 0);
+        RowIn<W, LOGN> rin = row_conv_load<W, LOGN>(Yf, Yg, 0);
         for (int r0 = 0; r0 < G::Bn - G::SR; r0 += G::SR) {
-            const RowIn<LOGN> nxt = row_conv_load<LOGN>(Yf, Yg, r0 + G::SR);
-            row_conv_compute<LOGN>(rin, Yf, r0, p, L);
+            const RowIn<W, LOGN> nxt = row_conv_load<W, LOGN>(Yf, Yg, r0 + G::SR);
+            row_conv_compute<W, LOGN>(rin, Yf, r0, p, L);
             rin = nxt;
         }
-        row_conv_compute<LOGN>(rin, Yf, G::Bn - G::SR, p, L);
+        row_conv_compute<W, LOGN>(rin, Yf, G::Bn - G::SR, p, L);
         __syncthreads();
-        ColInvIn<LOGN> iin = col_inv_load<LOGN>(Yf, 0);
+        ColInvIn<W, LOGN> iin = col_inv_load<W, LOGN>(Yf, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
-            const ColInvIn<LOGN> nxt = col_inv_load<LOGN>(Yf, c0 + G::SC);
-            col_inv_compute<LOGN, false>(iin, h + off, c0, p, L);
+            const ColInvIn<W, LOGN> nxt = col_inv_load<W, LOGN>(Yf, c0 + G::SC);
+            col_inv_compute<W, LOGN, false>(iin, h + off, c0, p, L);
             iin = nxt;
         }
-        col_inv_compute<LOGN, false>(iin, h + off, CL, p, L);
+        col_inv_compute<W, LOGN, false>(iin, h + off, CL, p, L);
         __syncthreads();
     }
 }
 
 // Sets *flag when some x[i] >= m.
-__global__ void k_range_check(const uint32_t* __restrict__ x, uint64_t n, uint32_t m, uint32_t* flag) {
+template <class T>
+__global__ void k_range_check(const T* __restrict__ x, uint64_t n, T m, uint32_t* flag) {
     uint32_t bad = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         bad |= (x[i] >= m) ? 1u : 0u;
     if (bad) atomicOr(flag, 1u);
 }
 
-hipError_t launch_range_check(const uint32_t* x, uint64_t n, uint32_t m, uint32_t* flag, hipStream_t st) {
+hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st) {
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return e;
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_range_check, dim3((uint32_t)blocks), dim3(256), 0, st, x, n, m, flag);
+    if (wbits == 32)
+        hipLaunchKernelGGL(k_range_check<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint32_t*)x, n,
+                           (uint32_t)m, flag);
+    else
+        hipLaunchKernelGGL(k_range_check<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint64_t*)x, n,
+                           (uint64_t)m, flag);
     return hipGetLastError();
 }
 
@@ -539,16 +587,47 @@ hipError_t launch_range_check(const uint32_t* x, uint64_t n, uint32_t m, uint32_
 #define NTT_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 #define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
 
-hipError_t launch_conv_small(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, const uint64_t* offs,
+template <class W>
+static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
+                               const DevPlan& p, hipStream_t st) {
+    using T = typename W::word;
+    switch (logn) {
+#define CASE(n)                                                                                                   \
+    case n: {                                                                                                     \
+        const uint32_t S = small_s(1 << n);                                                                       \
+        hipLaunchKernelGGL((k_conv_small<W, 1 << n>), dim3((count + S - 1) / S), dim3(256), 0, st, (const T*)f,      \
+                           (const T*)g, (T*)h, offs, count, p);                                                   \
+        return hipGetLastError();                                                                                 \
+    }
+        NTT_SMALL_CASES(CASE)
+#undef CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
                              uint32_t count, const DevPlan& p, hipStream_t st) {
     if (count == 0) return hipSuccess;
+    return wbits == 32 ? conv_small_t<W32>(logn, f, g, h, offs, count, p, st)
+                       : conv_small_t<W64>(logn, f, g, h, offs, count, p, st);
+}
+
+template <class W>
+static hipError_t ntt_small_t(int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
+                              hipStream_t st) {
+    using T = typename W::word;
     switch (logn) {
-#define CASE(n)                                                                                   \
-    case n: {                                                                                     \
-        const uint32_t S = small_s(1 << n);                                                       \
-        hipLaunchKernelGGL(k_conv_small<1 << n>, dim3((count + S - 1) / S), dim3(256), 0, st, f, g, h, \
-                           offs, count, p);                                                       \
-        return hipGetLastError();                                                                 \
+#define CASE(n)                                                                                                   \
+    case n: {                                                                                                     \
+        const uint32_t S = small_s(1 << n);                                                                       \
+        if (inv)                                                                                                  \
+            hipLaunchKernelGGL((k_ntt_small<W, 1 << n, true>), dim3((batch + S - 1) / S), dim3(256), 0, st,       \
+                               (const T*)x, (T*)X, batch, p);                                                     \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_ntt_small<W, 1 << n, false>), dim3((batch + S - 1) / S), dim3(256), 0, st,      \
+                               (const T*)x, (T*)X, batch, p);                                                     \
+        return hipGetLastError();                                                                                 \
     }
         NTT_SMALL_CASES(CASE)
 #undef CASE
@@ -557,44 +636,71 @@ hipError_t launch_conv_small(int logn, const uint32_t* f, const uint32_t* g, uin
     }
 }
 
-hipError_t launch_ntt_small(int logn, bool inv, const uint32_t* x, uint32_t* X, uint32_t batch, const DevPlan& p,
+hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
                             hipStream_t st) {
     if (batch == 0) return hipSuccess;
+    return wbits == 32 ? ntt_small_t<W32>(logn, inv, x, X, batch, p, st)
+                       : ntt_small_t<W64>(logn, inv, x, X, batch, p, st);
+}
+
+template <class W>
+static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* h, uint32_t items,
+                                  uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st) {
+    using T = typename W::word;
+    using SW = typename W::sword;
     switch (logn) {
-#define CASE(n)                                                                                          \
-    case n: {                                                                                            \
-        const uint32_t S = small_s(1 << n);                                                              \
-        if (inv)                                                                                         \
-            hipLaunchKernelGGL((k_ntt_small<1 << n, true>), dim3((batch + S - 1) / S), dim3(256), 0, st, x, X, \
-                               batch, p);                                                                \
-        else                                                                                             \
-            hipLaunchKernelGGL((k_ntt_small<1 << n, false>), dim3((batch + S - 1) / S), dim3(256), 0, st, x, \
-                               X, batch, p);                                                             \
-        return hipGetLastError();                                                                        \
+#define CASE(n)                                                                                                   \
+    case n: {                                                                                                     \
+        using G = FS<n>;                                                                                          \
+        const uint64_t ys = 2ull * G::N;                                                                          \
+        SW* Yf = (SW*)scratch;                                                                                    \
+        SW* Yg = Yf + G::N;                                                                                       \
+        hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)f, Yf,     \
+                           item_stride, ys, p);                                                                   \
+        hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)g, Yg,     \
+                           item_stride, ys, p);                                                                   \
+        hipLaunchKernelGGL((k_fs_row_conv<W, n>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf, (const SW*)Yg, \
+                           ys, p);                                                                                \
+        hipLaunchKernelGGL((k_fs_col_inv<W, n, false>), dim3(G::A / G::SC, items), dim3(G::T), 0, st,              \
+                           (const SW*)Yf, (T*)h, item_stride, ys, p);                                             \
+        return hipGetLastError();                                                                                 \
     }
-        NTT_SMALL_CASES(CASE)
+        NTT_LARGE_CASES(CASE)
 #undef CASE
         default:
             return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_conv_fourstep(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, uint32_t items,
-                                uint64_t item_stride, int32_t* scratch, const DevPlan& p, hipStream_t st) {
+hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
+                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st) {
     if (items == 0) return hipSuccess;
+    return wbits == 32 ? conv_fourstep_t<W32>(logn, f, g, h, items, item_stride, scratch, p, st)
+                       : conv_fourstep_t<W64>(logn, f, g, h, items, item_stride, scratch, p, st);
+}
+
+template <class W>
+static hipError_t ntt_fourstep_t(int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
+                                 const DevPlan& p, hipStream_t st) {
+    using T = typename W::word;
+    using SW = typename W::sword;
     switch (logn) {
-#define CASE(n)                                                                                               \
-    case n: {                                                                                                 \
-        using G = FS<n>;                                                                                      \
-        const uint64_t ys = 2ull * G::N;                                                                      \
-        int32_t* Yf = scratch;                                                                                \
-        int32_t* Yg = scratch + G::N;                                                                         \
-        hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, items), dim3(G::T), 0, st, f, Yf, item_stride, ys, p); \
-        hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, items), dim3(G::T), 0, st, g, Yg, item_stride, ys, p); \
-        hipLaunchKernelGGL(k_fs_row_conv<n>, dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf, (const int32_t*)Yg, ys, p); \
-        hipLaunchKernelGGL((k_fs_col_inv<n, false>), dim3(G::A / G::SC, items), dim3(G::T), 0, st,           \
-                           (const int32_t*)Yf, h, item_stride, ys, p);                                        \
-        return hipGetLastError();                                                                             \
+#define CASE(n)                                                                                                   \
+    case n: {                                                                                                     \
+        using G = FS<n>;                                                                                          \
+        const uint64_t N = G::N;                                                                                  \
+        if (!inv) {                                                                                               \
+            hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st, (const T*)x,   \
+                               (SW*)scratch, N, N, p);                                                            \
+            hipLaunchKernelGGL((k_fs_row_fwd_nat<W, n>), dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,           \
+                               (const SW*)scratch, (T*)X, N, N, p);                                               \
+        } else {                                                                                                  \
+            hipLaunchKernelGGL((k_fs_row_inv_nat<W, n>), dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,           \
+                               (const T*)x, (SW*)scratch, N, N, p);                                               \
+            hipLaunchKernelGGL((k_fs_col_inv<W, n, true>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st,          \
+                               (const SW*)scratch, (T*)X, N, N, p);                                               \
+        }                                                                                                         \
+        return hipGetLastError();                                                                                 \
     }
         NTT_LARGE_CASES(CASE)
 #undef CASE
@@ -603,39 +709,23 @@ hipError_t launch_conv_fourstep(int logn, const uint32_t* f, const uint32_t* g, 
     }
 }
 
-hipError_t launch_ntt_fourstep(int logn, bool inv, const uint32_t* x, uint32_t* X, uint32_t batch,
-                               int32_t* scratch, const DevPlan& p, hipStream_t st) {
+hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
+                               const DevPlan& p, hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    switch (logn) {
-#define CASE(n)                                                                                               \
-    case n: {                                                                                                 \
-        using G = FS<n>;                                                                                      \
-        const uint64_t N = G::N;                                                                              \
-        if (!inv) {                                                                                           \
-            hipLaunchKernelGGL(k_fs_col_fwd<n>, dim3(G::A / G::SC, batch), dim3(G::T), 0, st, x, scratch, N, N, p); \
-            hipLaunchKernelGGL(k_fs_row_fwd_nat<n>, dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,              \
-                               (const int32_t*)scratch, X, N, N, p);                                          \
-        } else {                                                                                              \
-            hipLaunchKernelGGL(k_fs_row_inv_nat<n>, dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st, x, scratch, N, N, p); \
-            hipLaunchKernelGGL((k_fs_col_inv<n, true>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st,          \
-                               (const int32_t*)scratch, X, N, N, p);                                          \
-        }                                                                                                     \
-        return hipGetLastError();                                                                             \
-    }
-        NTT_LARGE_CASES(CASE)
-#undef CASE
-        default:
-            return hipErrorInvalidValue;
-    }
+    return wbits == 32 ? ntt_fourstep_t<W32>(logn, inv, x, X, batch, scratch, p, st)
+                       : ntt_fourstep_t<W64>(logn, inv, x, X, batch, scratch, p, st);
 }
 
-hipError_t launch_conv_fused(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, const uint64_t* offs,
-                             uint32_t count, int32_t* scratch, uint32_t grid, const DevPlan& p, hipStream_t st) {
-    if (count == 0) return hipSuccess;
+template <class W>
+static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs,
+                               uint32_t count, void* scratch, uint32_t grid, const DevPlan& p, hipStream_t st) {
+    using T = typename W::word;
+    using SW = typename W::sword;
     switch (logn) {
-#define CASE(n)                                                                                             \
-    case n:                                                                                                 \
-        hipLaunchKernelGGL(k_conv_fused<n>, dim3(grid), dim3(FS<n>::T), 0, st, f, g, h, offs, count, scratch, p); \
+#define CASE(n)                                                                                                   \
+    case n:                                                                                                       \
+        hipLaunchKernelGGL((k_conv_fused<W, n>), dim3(grid), dim3(FS<n>::T), 0, st, (const T*)f, (const T*)g, (T*)h, \
+                           offs, count, (SW*)scratch, p);                                                         \
         return hipGetLastError();
         NTT_LARGE_CASES(CASE)
 #undef CASE
@@ -644,18 +734,39 @@ hipError_t launch_conv_fused(int logn, const uint32_t* f, const uint32_t* g, uin
     }
 }
 
-int fused_blocks_per_cu(int logn) {
+hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
+                             uint32_t count, void* scratch, uint32_t grid, const DevPlan& p, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    return wbits == 32 ? conv_fused_t<W32>(logn, f, g, h, offs, count, scratch, grid, p, st)
+                       : conv_fused_t<W64>(logn, f, g, h, offs, count, scratch, grid, p, st);
+}
+
+template <class W>
+static int fused_bpc_t(int logn) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (logn) {
 #define CASE(n) \
-    case n: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fused<n>, FS<n>::T, 0); break;
+    case n: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fused<W, n>, FS<n>::T, 0); break;
         NTT_LARGE_CASES(CASE)
 #undef CASE
         default:
             break;
     }
     return e == hipSuccess ? nb : 0;
+}
+
+int fused_blocks_per_cu(int wbits, int logn) { return wbits == 32 ? fused_bpc_t<W32>(logn) : fused_bpc_t<W64>(logn); }
+
+int fused_threads(int logn) {
+    switch (logn) {
+#define CASE(n) \
+    case n: return FS<n>::T;
+        NTT_LARGE_CASES(CASE)
+#undef CASE
+        default:
+            return 0;
+    }
 }
 
 }  // namespace nttmi

@@ -18,21 +18,23 @@ struct DevPlan {
 };
 
 constexpr int SMALL_MAX_LOG2N = 12;
-constexpr int MAX_LOG2N = 22;   // 32-bit words: m < 2^24, and no such prime has nu = 2^23
+constexpr int MAX_LOG2N = 22;   // no prime below 2^24 has nu = 2^23; 64-bit words use the same kernels
 
-hipError_t launch_conv_small(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, const uint64_t* offs,
+// wbits = 32 (uint32 words, m < 2^24) or 64 (uint64 words, m < 2^50).
+hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
                              uint32_t count, const DevPlan& p, hipStream_t st);
-hipError_t launch_ntt_small(int logn, bool inv, const uint32_t* x, uint32_t* X, uint32_t batch, const DevPlan& p,
+hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
                             hipStream_t st);
-// scratch: items * 2N words (conv), batch * N words (ntt)
-hipError_t launch_conv_fourstep(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, uint32_t items,
-                                uint64_t item_stride, int32_t* scratch, const DevPlan& p, hipStream_t st);
-hipError_t launch_ntt_fourstep(int logn, bool inv, const uint32_t* x, uint32_t* X, uint32_t batch,
-                               int32_t* scratch, const DevPlan& p, hipStream_t st);
-// scratch: grid * 2N words
-hipError_t launch_conv_fused(int logn, const uint32_t* f, const uint32_t* g, uint32_t* h, const uint64_t* offs,
-                             uint32_t count, int32_t* scratch, uint32_t grid, const DevPlan& p, hipStream_t st);
-int fused_blocks_per_cu(int logn);
-hipError_t launch_range_check(const uint32_t* x, uint64_t n, uint32_t m, uint32_t* flag, hipStream_t st);
+// scratch: items * 2N scratch words (conv), batch * N (ntt); scratch words are wbits/8 bytes
+hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
+                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st);
+hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
+                               const DevPlan& p, hipStream_t st);
+// scratch: grid * 2N scratch words
+hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
+                             uint32_t count, void* scratch, uint32_t grid, const DevPlan& p, hipStream_t st);
+int fused_blocks_per_cu(int wbits, int logn);
+int fused_threads(int logn);
+hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st);
 
 }  // namespace nttmi

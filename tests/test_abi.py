@@ -98,3 +98,15 @@ def test_ntt_validation_errors(lib):
         assert fn(641, 6, 3, 32, BAD, BAD, 1, 0, None) == 4
         assert fn(M, 4, pow(2, 2 ** 15, M), 32, BAD, BAD, 0, 0, None) == 0  # empty batch: nothing to do
         assert fn(M, 4, pow(2, 2 ** 15, M), 32, None, BAD, 1, 0, None) == 1
+
+
+def test_u64_validation(lib):
+    m = 31065037602817
+    c = lib.conv_circular
+    # root of the wrong order for 64-bit words
+    assert c(m, 10, 2, 64, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 4
+    # 2^19 does not divide nu = 2^18
+    assert c(m, 19, 2, 64, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 3
+    # a 58-bit Rader prime (order of 2 is 2^28) is valid but beyond exact fp64 residues
+    m58 = 231292694251438081
+    assert c(m58, 10, pow(2, 2 ** 18, m58), 64, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 8
