@@ -66,11 +66,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
+    ap.add_argument("--workload", choices=["batch", "serve"], default="batch",
+                    help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests")
+    ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the batch would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve":
+        return serve_bench(args)
 
     import torch
     import paper_1005_1497_amd as nt
@@ -169,6 +176,80 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f_h, g_h, m, N)
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Serving: Poisson arrivals of convolution requests, lengths 2^n with n
+    uniform in [8, 18], m = 31065037602817 (64-bit words), continuous batching
+    over two streams; p50/p99 latency and throughput at offered load
+    rho * (saturated throughput), against one launch sequence per request."""
+    import threading
+
+    import paper_1005_1497_amd.serve as sv
+    import seeded_inputs as si
+
+    m = si.M_U64
+    warm, n = 200, args.requests
+    lens = si.served_lengths(warm + n, seed=5)
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    reqs = [(rng.integers(0, m, 1 << int(k), dtype=np.uint64), rng.integers(0, m, 1 << int(k), dtype=np.uint64))
+            for k in lens]
+    log("drew %d requests (%.1f M elements) in %.1f s" % (len(reqs), sum(1 << int(k) for k in lens) / 1e6,
+                                                         time.perf_counter() - t0))
+    cap = 24   # 2^24 elements per arena (3 arenas x 128 MiB)
+
+    def run(reqs_, rate, max_batch):
+        ex = sv.GpuExecutor(m, capacity_log2=cap, elem_bits=64, streams=2)
+        srv = sv.ConvServer(ex, capacity_log2=cap, max_batch=max_batch, max_inflight=4).start()
+        for f, g in reqs_[:warm]:
+            srv.submit(f, g)
+        srv.drain()
+        srv.stats = sv.ServeStats()
+        body = reqs_[warm:]
+        gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
+        t_start = time.perf_counter()
+
+        def client():
+            nxt = time.perf_counter()
+            for (f, g), gap in zip(body, gaps):
+                nxt += gap
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                srv.submit(f, g)
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        srv.drain()
+        el = time.perf_counter() - t_start
+        srv.stop()
+        st = srv.stats
+        return {"throughput_conv_per_s": len(body) / el, "p50_ms": st.percentile(50) * 1e3,
+                "p99_ms": st.percentile(99) * 1e3, "mean_batch": float(np.mean(st.batch_sizes)),
+                "peak_inflight_batches": st.peak_inflight, "elapsed_s": el}
+
+    sat = run(reqs, None, 512)
+    log("closed loop: %.0f conv/s" % sat["throughput_conv_per_s"])
+    rate = args.rho * sat["throughput_conv_per_s"]
+    served = run(reqs, rate, 512)
+    log("served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (rate, served["p50_ms"], served["p99_ms"]))
+    single_sat = run(reqs, None, 1)
+    single = run(reqs, args.rho * single_sat["throughput_conv_per_s"], 1)
+    single_at_rate = run(reqs, rate, 1) if rate <= single_sat["throughput_conv_per_s"] else None
+    out = {
+        "metric": "served exact convolutions: throughput and p50/p99 latency",
+        "value": served["throughput_conv_per_s"], "unit": "conv/s", "n_gpus": 1, "steps": n, "warmup": warm,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"]},
+        "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "rho": args.rho, "offered_per_s": rate,
+                   "words": "u64", "streams": 2},
+        "saturated": sat, "served": served,
+        "forms": {"one_launch_per_request_saturated": single_sat, "one_launch_per_request_at_rho": single,
+                  "one_launch_per_request_at_same_rate": single_at_rate},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,311 @@
+"""Served form: continuous batching of exact circular convolutions.
+
+Requests (f, g) of power-of-two lengths arrive at any time.  A scheduler thread
+
+  1. admits queued requests, in arrival order, while device memory allows:
+     each request takes one slot of its length from a buddy allocator over
+     three equal device arenas (F, G, H), so one offset is valid in all three;
+  2. copies the admitted requests' operands into their slots and launches them
+     together as ONE conv_batched call (the fused forward / pointwise /
+     inverse kernels) on the next of several HIP streams, so that batches
+     admitted while others are still running overlap on the device;
+  3. copies each result back, completes the request's future and frees its
+     slot, which lets further requests in.
+
+Operands stay resident in the arenas from admission to completion.  Latency is
+completion time minus arrival time on the host monotonic clock.
+
+All arithmetic runs in the library's HIP kernels through conv_batched; this
+module only schedules, allocates and copies.  The executor is pluggable so the
+scheduling logic can be exercised without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+class BuddyAllocator:
+    """Power-of-two buddy allocator over [0, 2^total_log2) elements.
+
+    alloc(k) returns the offset of a free block of 2^k elements aligned to 2^k,
+    or None when no such block is free; free(offset, k) returns it and merges
+    buddies."""
+
+    def __init__(self, total_log2: int, min_log2: int = 0):
+        if min_log2 > total_log2:
+            raise ValueError("min block larger than the arena")
+        self.total_log2 = total_log2
+        self.min_log2 = min_log2
+        self.free_lists = {k: set() for k in range(min_log2, total_log2 + 1)}
+        self.free_lists[total_log2].add(0)
+        self.used = 0
+
+    def alloc(self, k: int):
+        k = max(k, self.min_log2)
+        if k > self.total_log2:
+            return None
+        j = k
+        while j <= self.total_log2 and not self.free_lists[j]:
+            j += 1
+        if j > self.total_log2:
+            return None
+        off = min(self.free_lists[j])
+        self.free_lists[j].remove(off)
+        while j > k:                 # split, keep the lower half
+            j -= 1
+            self.free_lists[j].add(off + (1 << j))
+        self.used += 1 << k
+        return off
+
+    def free(self, off: int, k: int):
+        k = max(k, self.min_log2)
+        self.used -= 1 << k
+        while k < self.total_log2:
+            buddy = off ^ (1 << k)
+            if buddy in self.free_lists[k]:
+                self.free_lists[k].remove(buddy)
+                off = min(off, buddy)
+                k += 1
+            else:
+                break
+        self.free_lists[k].add(off)
+
+    @property
+    def capacity(self) -> int:
+        return 1 << self.total_log2
+
+
+@dataclass
+class Request:
+    rid: int
+    staged: object          # executor-specific staging of f, g and the output
+    log2n: int
+    arrival: float
+    future: concurrent.futures.Future
+    offset: int = -1
+    done_time: float = 0.0
+    out: np.ndarray = None
+    cancelled: bool = False
+
+
+@dataclass
+class _Batch:
+    reqs: list
+    handle: object
+    stream_id: int
+    launched: float
+
+
+@dataclass
+class ServeStats:
+    latencies: list = field(default_factory=list)
+    batch_sizes: list = field(default_factory=list)
+    peak_used: int = 0
+    peak_inflight: int = 0
+    completed: int = 0
+
+    def percentile(self, q: float) -> float:
+        return float(np.percentile(np.array(self.latencies), q)) if self.latencies else float("nan")
+
+
+class GpuExecutor:
+    """Device side of the server: arenas, streams and conv_batched launches."""
+
+    def __init__(self, m: int, capacity_log2: int, elem_bits: int = 64, streams: int = 2, device: int = 0,
+                 root: int = 2, root_log2order: int | None = None):
+        import torch
+        import paper_1005_1497_amd as nt
+        self.torch, self.nt = torch, nt
+        self.m = m
+        self.elem_bits = elem_bits
+        self.dtype = torch.int64 if elem_bits == 64 else torch.int32
+        self.np_dtype = np.uint64 if elem_bits == 64 else np.uint32
+        self.dev = torch.device("cuda", device)
+        n = 1 << capacity_log2
+        self.F = torch.zeros(n, dtype=self.dtype, device=self.dev)
+        self.G = torch.zeros(n, dtype=self.dtype, device=self.dev)
+        self.H = torch.zeros(n, dtype=self.dtype, device=self.dev)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
+        self.root = root
+        self.rlo = root_log2order if root_log2order is not None else nt.modulus_order(m)
+
+    def prepare(self, f: np.ndarray, g: np.ndarray):
+        """Runs on the submitting thread: pinned host copies of the operands
+        and a pinned buffer for the result."""
+        n = f.size
+        t = self.torch.empty((3, n), dtype=self.dtype, pin_memory=True)
+        v = t.numpy().view(self.np_dtype)
+        v[0] = f
+        v[1] = g
+        return t
+
+    def launch(self, reqs, stream_id: int):
+        """Copies operands in, runs one conv_batched over the requests, copies
+        results out; returns a handle to poll."""
+        torch, nt = self.torch, self.nt
+        s = self.streams[stream_id]
+        with torch.cuda.stream(s):
+            for r in reqs:
+                N = 1 << r.log2n
+                self.F[r.offset:r.offset + N].copy_(r.staged[0], non_blocking=True)
+                self.G[r.offset:r.offset + N].copy_(r.staged[1], non_blocking=True)
+            desc = nt.BatchDesc([r.log2n for r in reqs], [r.offset for r in reqs])
+            nt.conv_batched(self.F, self.G, desc, self.m, root=self.root, root_log2order=self.rlo, out=self.H,
+                            stream=s)
+            for r in reqs:
+                N = 1 << r.log2n
+                r.staged[2].copy_(self.H[r.offset:r.offset + N], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (ev, [r.staged for r in reqs], desc)
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle):
+        return [t[2].numpy().view(self.np_dtype).copy() for t in handle[1]]
+
+
+class ConvServer:
+    """Continuous-batching server over an executor (see module docstring)."""
+
+    def __init__(self, executor, capacity_log2: int, min_log2: int = 0, max_batch: int = 512,
+                 max_inflight: int = 4):
+        self.ex = executor
+        self.alloc = BuddyAllocator(capacity_log2, min_log2)
+        self.max_batch = max_batch
+        self.max_inflight = max_inflight
+        self.queue = collections.deque()
+        self.inflight = []
+        self.stats = ServeStats()
+        self._next_stream = 0
+        self._rid = 0
+        self._lock = threading.Lock()
+        self._wake = threading.Condition(self._lock)
+        self._stop = False
+        self._thread = None
+        self._outstanding = 0       # submitted and not yet completed, failed or cancelled
+        self.admission_log = []     # request ids in admission order
+
+    # ------------------------------------------------------------ client side
+    def submit(self, f: np.ndarray, g: np.ndarray) -> concurrent.futures.Future:
+        if f.shape != g.shape or f.ndim != 1 or f.size == 0 or f.size & (f.size - 1):
+            raise ValueError("f and g must be 1-D of the same power-of-two length")
+        log2n = int(f.size).bit_length() - 1
+        if log2n > self.alloc.total_log2:
+            raise ValueError("request larger than the device arena")
+        fut = concurrent.futures.Future()
+        arrival = time.monotonic()
+        staged = self.ex.prepare(f, g)
+        with self._lock:
+            r = Request(self._rid, staged, log2n, arrival, fut)
+            self._rid += 1
+            self._outstanding += 1
+            self.queue.append(r)
+            self._wake.notify()
+        fut.request = r
+        return fut
+
+    def cancel(self, fut) -> bool:
+        """Cancels a request that has not been admitted yet."""
+        with self._lock:
+            r = fut.request
+            if r.offset < 0 and r in self.queue:
+                self.queue.remove(r)
+                r.cancelled = True
+                self._outstanding -= 1
+                fut.cancel()
+                return True
+        return False
+
+    # ------------------------------------------------------------ scheduler
+    def start(self):
+        self._thread = threading.Thread(target=self._run, name="conv-server", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self, drain: bool = True):
+        if drain:
+            self.drain()
+        with self._lock:
+            self._stop = True
+            self._wake.notify()
+        if self._thread:
+            self._thread.join()
+
+    def drain(self, timeout: float = 600.0):
+        t0 = time.monotonic()
+        while True:
+            with self._lock:
+                if self._outstanding == 0:
+                    return
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError("server did not drain")
+            time.sleep(0.0005)
+
+    def _admit(self):
+        """Admits queued requests in arrival order while slots are free."""
+        admitted = []
+        while self.queue and len(admitted) < self.max_batch:
+            r = self.queue[0]
+            off = self.alloc.alloc(r.log2n)
+            if off is None:
+                break
+            self.queue.popleft()
+            r.offset = off
+            admitted.append(r)
+            self.admission_log.append(r.rid)
+        self.stats.peak_used = max(self.stats.peak_used, self.alloc.used)
+        return admitted
+
+    def _complete(self, b: _Batch):
+        outs = self.ex.results(b.handle)
+        now = time.monotonic()
+        for r, o in zip(b.reqs, outs):
+            r.out = o
+            r.done_time = now
+            self.alloc.free(r.offset, r.log2n)
+            self.stats.latencies.append(now - r.arrival)
+            self.stats.completed += 1
+            self._outstanding -= 1
+            r.future.set_result(o)
+
+    def _run(self):
+        while True:
+            with self._lock:
+                if self._stop:
+                    return
+                admitted = self._admit() if len(self.inflight) < self.max_inflight else []
+            if admitted:
+                sid = self._next_stream % len(self.ex.streams)
+                self._next_stream += 1
+                try:
+                    h = self.ex.launch(admitted, sid)
+                except Exception as e:          # a failed launch fails its requests only
+                    with self._lock:
+                        for r in admitted:
+                            self.alloc.free(r.offset, r.log2n)
+                            self._outstanding -= 1
+                            r.future.set_exception(e)
+                    continue
+                with self._lock:
+                    self.inflight.append(_Batch(admitted, h, sid, time.monotonic()))
+                    self.stats.batch_sizes.append(len(admitted))
+                    self.stats.peak_inflight = max(self.stats.peak_inflight, len(self.inflight))
+            done = [b for b in list(self.inflight) if self.ex.poll(b.handle)]
+            if done:
+                with self._lock:
+                    for b in done:
+                        self.inflight.remove(b)
+                        self._complete(b)
+            if not admitted and not done:
+                with self._lock:
+                    if not self._stop and (not self.queue or len(self.inflight) >= self.max_inflight
+                                           or self.alloc.used == self.alloc.capacity):
+                        self._wake.wait(timeout=0.0002)
