@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -21,6 +22,8 @@ struct Plan {
     double2* dP = nullptr;
     double* dTT = nullptr;
     double* dTTi = nullptr;
+    uint32_t* dTT32 = nullptr;
+    uint32_t* dTTi32 = nullptr;
 };
 
 struct Buf {
@@ -155,11 +158,22 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
             }
         he = upload(&p.dTT, tt);
         if (he == hipSuccess) he = upload(&p.dTTi, tti);
+        if (he == hipSuccess && m < (1ull << 32)) {
+            std::vector<uint32_t> t32(N), ti32(N);
+            for (uint64_t e = 0; e < N; ++e) {
+                t32[e] = (uint32_t)tt[e];
+                ti32[e] = (uint32_t)tti[e];
+            }
+            he = upload(&p.dTT32, t32);
+            if (he == hipSuccess) he = upload(&p.dTTi32, ti32);
+        }
     }
     if (he != hipSuccess) {
         if (p.dP) (void)hipFree(p.dP);
         if (p.dTT) (void)hipFree(p.dTT);
         if (p.dTTi) (void)hipFree(p.dTTi);
+        if (p.dTT32) (void)hipFree(p.dTT32);
+        if (p.dTTi32) (void)hipFree(p.dTTi32);
         return hip_status(he);
     }
     // N^-1 = 2^-n = 2^(nu - n) mod m: the multiplicative inverse of N (Appendix A)
@@ -167,6 +181,8 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     p.dev.P = p.dP;
     p.dev.TT = p.dTT;
     p.dev.TTi = p.dTTi;
+    p.dev.TT32 = p.dTT32;
+    p.dev.TTi32 = p.dTTi32;
     p.dev.M = make_modc(m);
     p.dev.ninv = (double)ninv;
     p.dev.ninvq = (double)ninv / (double)m;
@@ -474,6 +490,8 @@ void ntt_release_caches(void) {
         if (kv.second.dP) (void)hipFree(kv.second.dP);
         if (kv.second.dTT) (void)hipFree(kv.second.dTT);
         if (kv.second.dTTi) (void)hipFree(kv.second.dTTi);
+        if (kv.second.dTT32) (void)hipFree(kv.second.dTT32);
+        if (kv.second.dTTi32) (void)hipFree(kv.second.dTTi32);
     }
     c.plans.clear();
     for (auto& kv : c.work) if (kv.second.ptr) (void)hipFree(kv.second.ptr);

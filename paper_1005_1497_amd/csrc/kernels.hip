@@ -12,6 +12,9 @@
 // phase runs forward(f), forward(g), product, inverse and the inverse twiddle
 // on each row, and the last phase runs the inverse column transforms.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
+
 #include "blockdft.hpp"
 #include "launch.hpp"
 
@@ -119,6 +122,9 @@ struct FS {
 // return 0 and out-of-range writes are dropped).  Accesses take a per-lane
 // byte offset and a wave-uniform byte offset, so that the strided accesses of
 // a work item cost no per-element address arithmetic.
+#ifndef NTT_STREAM_AUX
+#define NTT_STREAM_AUX 2   // cache policy of streamed operands: non-temporal
+#endif
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
     __device__ __forceinline__ Buf(const void* p, uint32_t bytes)
@@ -135,6 +141,13 @@ struct Buf {
     __device__ __forceinline__ void st32(uint32_t x, uint32_t v, uint32_t s) const {
         __builtin_amdgcn_raw_buffer_store_b32(x, r, v, s, 0);
     }
+    // streaming (non-temporal) variants for operands read or written once
+    __device__ __forceinline__ uint32_t ld32s(uint32_t v, uint32_t s) const {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, v, s, NTT_STREAM_AUX);
+    }
+    __device__ __forceinline__ void st32s(uint32_t x, uint32_t v, uint32_t s) const {
+        __builtin_amdgcn_raw_buffer_store_b32(x, r, v, s, NTT_STREAM_AUX);
+    }
     __device__ __forceinline__ uint64_t ld64(uint32_t v, uint32_t s) const {
         return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
     }
@@ -143,6 +156,33 @@ struct Buf {
                                               r, v, s, 0);
     }
 };
+
+// Four-step twiddle w^(+-t1 u2) from the plan's tables: 32-bit words when the
+// modulus fits (half the bytes and registers of the fp64 table).
+template <class W>
+struct Tw4 {
+    using T = typename std::conditional<W::WB == 4, uint32_t, double>::type;
+    __device__ static __forceinline__ Buf buf(const DevPlan& p, bool inv, uint32_t n) {
+        if constexpr (W::WB == 4) return Buf(inv ? p.TTi32 : p.TT32, n * 4u);
+        else return Buf(inv ? p.TTi : p.TT, n * 8u);
+    }
+    __device__ static __forceinline__ T ld(const Buf& b, uint32_t ve, uint32_t se) {
+        if constexpr (W::WB == 4) return b.ld32(ve * 4u, se * 4u);
+        else return b.ld64f(ve * 8u, se * 8u);
+    }
+};
+
+// Word accesses of streamed operands (read or written once per launch).
+template <class W>
+__device__ __forceinline__ typename W::word ld_word_s(const Buf& b, uint32_t ve, uint32_t se) {
+    if constexpr (W::WB == 4) return b.ld32s(ve * 4u, se * 4u);
+    else return b.ld64(ve * 8u, se * 8u);
+}
+template <class W>
+__device__ __forceinline__ void st_word_s(const Buf& b, typename W::word x, uint32_t ve, uint32_t se) {
+    if constexpr (W::WB == 4) b.st32s(x, ve * 4u, se * 4u);
+    else b.st64(x, ve * 8u, se * 8u);
+}
 
 // Word and scratch accesses by element offsets (per-lane, uniform).
 template <class W>
@@ -262,7 +302,7 @@ __device__ __forceinline__ ColIn<W, LOGN> col_fwd_load(const typename W::word* x
     const Buf bx(x, G::N * W::WB);
     ColIn<W, LOGN> in;
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) in.w[i] = ld_word<W>(bx, c0 + s + G::A * j, G::A * B::pos0(0, i));
+    for (int i = 0; i < B::E; ++i) in.w[i] = ld_word_s<W>(bx, c0 + s + G::A * j, G::A * B::pos0(0, i));
     return in;
 }
 
@@ -277,18 +317,19 @@ __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typena
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int t1 = c0 + s;
-    const Buf by(Y, G::N * W::SB), bt(p.TT, G::N * 8u);
+    const Buf by(Y, G::N * W::SB), bt = Tw4<W>::buf(p, false, G::N);
     double v[B::E];
     // four-step twiddles, loaded ahead of the transform
-    double tw4[B::E];
+    typename Tw4<W>::T tw4[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f((j * G::A + t1) * 8u, B::posL(0, i) * G::A * 8u);
+    for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, j * G::A + t1, B::posL(0, i) * G::A);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(in.w[i], M);
     block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
                                                    TwTab<W, G::Bn>{L.colf, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], tw4[i], M), j * G::A + t1, B::posL(0, i) * G::A);
+    for (int i = 0; i < B::E; ++i)
+        st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), j * G::A + t1, B::posL(0, i) * G::A);
 }
 
 template <class W, int LOGN>
@@ -331,7 +372,7 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf bf(Yf, G::N * W::SB), bt(p.TTi, G::N * 8u);
+    const Buf bf(Yf, G::N * W::SB), bt = Tw4<W>::buf(p, true, G::N);
     const uint32_t rowoff = (uint32_t)(u2 * G::A + j);
     double F[B::E], v[B::E];
 #pragma unroll
@@ -357,13 +398,13 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
         for (int i = 0; i < B::E; ++i) v[i] = L.xch[B::lds(s, B::pos0(j, i))];
         __syncthreads();
     }
-    double tw4[B::E];
+    typename Tw4<W>::T tw4[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f(rowoff * 8u, B::posL(0, i) * 8u);
+    for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, rowoff, B::posL(0, i));
     block_dft_tw<W, G::A, G::SR, POS_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
                                                  TwTab<W, G::A>{L.rowi, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], tw4[i], M), rowoff, B::posL(0, i));
+    for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i));
 }
 
 template <class W, int LOGN>
@@ -410,7 +451,7 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
         const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
-        st_word<W>(bx, W::canon(y, M), off, B::posL(0, i) * G::A);
+        st_word_s<W>(bx, W::canon(y, M), off, B::posL(0, i) * G::A);
     }
 }
 
@@ -451,17 +492,17 @@ __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typ
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf bx(X, G::N * W::WB), by(Y, G::N * W::SB), bt(p.TTi, G::N * 8u);
+    const Buf bx(X, G::N * W::WB), by(Y, G::N * W::SB), bt = Tw4<W>::buf(p, true, G::N);
     double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(ld_word<W>(bx, u2 + G::Bn * j, G::Bn * B::pos0(0, i)), M);
-    double tw4[B::E];
+    typename Tw4<W>::T tw4[B::E];
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) tw4[i] = bt.ld64f((u2 * G::A + j) * 8u, B::posL(0, i) * 8u);
+    for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, u2 * G::A + j, B::posL(0, i));
     block_dft_tw<W, G::A, G::SR, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
                                                  TwTab<W, G::A>{L.rowi, M});
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], tw4[i], M), u2 * G::A + j, B::posL(0, i));
+    for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), u2 * G::A + j, B::posL(0, i));
 }
 
 // Kernels of the multi-launch four-step (grid.y = item / row of the batch).
