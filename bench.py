@@ -92,8 +92,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
-    ap.add_argument("--workload", choices=["batch", "serve"], default="batch",
-                    help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words")
+    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single"], default="batch",
+                    help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
+                         "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests")
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -115,6 +116,10 @@ def main():
         return
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "uneven":
+        return uneven_bench(args)
+    if args.workload == "single":
+        return single_bench(args)
 
     import torch
     import paper_1005_1497_amd as nt
@@ -214,6 +219,73 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f_h, g_h, m, N)
     print(json.dumps(out), flush=True)
+
+
+def _time_ms(fn, reps, stream):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def uneven_bench(args):
+    """10000 convolutions of lengths 2^n, n uniform in [6, 19], m = 13631489,
+    packed back to back: one conv_batched call (one launch per length class)
+    against one launch sequence per item."""
+    import torch
+    import paper_1005_1497_amd as nt
+    import seeded_inputs as si
+    w = si.uneven_batch(10000)
+    f_h, g_h = si.operands(w)
+    dev = torch.device("cuda", 0)
+    f = torch.from_numpy(f_h.view(np.int32)).to(dev)
+    g = torch.from_numpy(g_h.view(np.int32)).to(dev)
+    h = torch.empty_like(f)
+    desc = nt.BatchDesc(w.log2n, si.offsets(w.log2n))
+    st = torch.cuda.current_stream()
+    run = lambda flags=0: nt.conv_batched(f, g, desc, w.m, out=h, flags=flags, stream=st)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    per = _time_ms(run, args.steps, st)
+    run(nt.FLAG_PER_ITEM)
+    torch.cuda.synchronize()
+    per_item = _time_ms(lambda: run(nt.FLAG_PER_ITEM), 2, st)
+    total = w.total_elems
+    out = {"metric": "exact convolutions/s, uneven batch", "value": 10000 / (per.mean() / 1e3), "unit": "conv/s",
+           "ms_per_step": float(per.mean()), "elements_per_s": total / (per.mean() / 1e3),
+           "hbm_gbs_algorithmic": 12 * total / (per.mean() / 1e3) / 1e9,
+           "config": {"workload": w.name, "total_elements": total},
+           "forms": {"per_item_ms": float(per_item.mean()), "per_item_conv_per_s": 10000 / (per_item.mean() / 1e3)}}
+    print(json.dumps(out), flush=True)
+
+
+def single_bench(args):
+    """Latency of one convolution: N = 1024 (root 2^512) and N = 2^19 (root 2,
+    operands in {0..3}), p50/p99 over repeated launches."""
+    import torch
+    import paper_1005_1497_amd as nt
+    import seeded_inputs as si
+    st = torch.cuda.current_stream()
+    res = {}
+    for w in (si.single_n1024(), si.single_n524288_small()):
+        f_h, g_h = si.operands(w)
+        f = torch.from_numpy(f_h.view(np.int32)).cuda()
+        g = torch.from_numpy(g_h.view(np.int32)).cuda()
+        h = torch.empty_like(f)
+        n = w.log2n[0]
+        run = lambda: nt.conv_circular(f, g, w.m, out=h, stream=st)
+        for _ in range(20):
+            run()
+        torch.cuda.synchronize()
+        per = _time_ms(run, 1000 if n <= 12 else 200, st)
+        res[w.name] = {"p50_us": float(np.percentile(per, 50) * 1e3), "p99_us": float(np.percentile(per, 99) * 1e3),
+                       "conv_per_s": 1e3 / float(per.mean())}
+    print(json.dumps({"metric": "single convolution latency", "results": res}), flush=True)
 
 
 def serve_bench(args):
