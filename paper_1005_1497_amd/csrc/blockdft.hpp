@@ -61,6 +61,21 @@ __device__ __forceinline__ void dft_reg(double* a, const double2* tw, int ts, co
 
 enum { SEQ_FAST = 0, POS_FAST = 1 };
 
+// Orders the LDS writes of an exchange before its reads.  When every sequence
+// lives in one wave, the wave's own LDS accesses complete in issue order, so
+// only the compiler must be kept from moving accesses across the point;
+// otherwise the whole workgroup waits.
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void xch_sync() {
+    if constexpr (WAVE_LOCAL) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Wave-uniform table read through the constant address space, so that it is
 // issued as a scalar load into SGPRs (the tables are never written by kernels).
 typedef __attribute__((address_space(4))) const double cdouble;
@@ -88,6 +103,9 @@ struct Blk {
     static constexpr int VL = E / RL;                  // virtual items in the last pass
     static constexpr int ROWP = (ORD == POS_FAST) ? (L + L / 16) : L;
     static constexpr int LDS_DOUBLES = (NP > 1) ? S * ROWP : 1;
+    // every sequence's W work items are lanes of one wave (POS_FAST, W | 64):
+    // its exchanges need no workgroup barrier
+    static constexpr bool WAVE_LOCAL = (ORD == POS_FAST) && (W <= 64) && (64 % W == 0);
 
     __device__ static __forceinline__ void item(int tid, int& s, int& j) {
         if (ORD == SEQ_FAST) { s = tid % S; j = tid / S; }
@@ -177,11 +195,11 @@ __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, i
             ldsbuf[B::lds(s, pos)] = v[i];
         }
         (void)Vp;
-        __syncthreads();
+        xch_sync<B::WAVE_LOCAL>();
         // read inputs of this pass (radix 16, one virtual item jv = j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = ldsbuf[B::lds(s, j + r * (L / 16))];
-        __syncthreads();
+        xch_sync<B::WAVE_LOCAL>();
         // inter-pass twiddles w_{16 Ns}^(r k) = w_L^((L/(16 Ns)) r k), k = j mod Ns
         twf(v, p, Ns, j & (Ns - 1));
         dft_reg<W, 16>(v, twE, 1, M);

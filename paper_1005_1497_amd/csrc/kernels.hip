@@ -61,10 +61,10 @@ __global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, c
         // positions of the inverse: reorder through LDS
 #pragma unroll
         for (int i = 0; i < B::E; ++i) lds[B::lds(s, B::posL(j, i))] = v[i];
-        __syncthreads();
+        xch_sync<B::WAVE_LOCAL>();
 #pragma unroll
         for (int i = 0; i < B::E; ++i) v[i] = lds[B::lds(s, B::pos0(j, i))];
-        __syncthreads();
+        xch_sync<B::WAVE_LOCAL>();
     }
     block_dft<W, L, S, POS_FAST, true>(v, lds, s, j, p.P, lshift, p.nmask, M);
     if (valid) {
@@ -213,23 +213,33 @@ __device__ __forceinline__ void st_scr(const Buf& b, double y, uint32_t ve, uint
 
 // Shared-memory layout of a four-step workgroup: the pass exchange buffer and
 // the per-pass twiddle tables of the column (length B) and row (length A)
-// transforms, forward and inverse (w only; w/m is formed at use).
+// transforms, forward and inverse.  Table entries are (w, w/m) pairs, which
+// save the quotient multiply of every inter-pass twiddle, unless the pairs
+// would push the workgroup out of two-per-CU residency or out of LDS; then
+// they hold w alone and w/m is formed at use.
+constexpr int LDS_HALF_CU = 80 * 1024;
 template <int LOGN>
 struct FSLds {
     using G = FS<LOGN>;
     static constexpr bool SAME = (G::A == G::Bn);
-    static constexpr int TC = PassTab<G::Bn>::SIZE;
-    static constexpr int TR = PassTab<G::A>::SIZE;
-    static constexpr int WORDS = G::XCH + 2 * TC + (SAME ? 0 : 2 * TR);
+    static constexpr int TC = PassTab<G::Bn>::SIZE;   // entries per column table
+    static constexpr int TR = PassTab<G::A>::SIZE;    // entries per row table
+    static constexpr int XCH2 = (G::XCH + 1) & ~1;     // tables start 16-byte aligned
+    static constexpr int ENTRIES = 2 * TC + (SAME ? 0 : 2 * TR);
+    static constexpr int BYTES1 = 8 * (XCH2 + ENTRIES);
+    static constexpr int BYTES2 = 8 * (XCH2 + 2 * ENTRIES);
+    static constexpr bool PAIRS = BYTES2 <= LDS_HALF_CU || (BYTES1 > LDS_HALF_CU && BYTES2 <= 150 * 1024);
+    using Entry = typename std::conditional<PAIRS, double2, double>::type;
+    static constexpr int WORDS = PAIRS ? BYTES2 / 8 : BYTES1 / 8;
     double* xch;
-    const double* colf;
-    const double* coli;
-    const double* rowf;
-    const double* rowi;
+    const Entry* colf;
+    const Entry* coli;
+    const Entry* rowf;
+    const Entry* rowi;
 };
 
-template <int L, bool INV>
-__device__ __forceinline__ void fill_pass_tab(double* t, const DevPlan& p, int logn) {
+template <int L, bool INV, class T>
+__device__ __forceinline__ void fill_pass_tab(T* t, const DevPlan& p, int logn) {
     using PT = PassTab<L>;
     using B = Blk<L, 1, SEQ_FAST>;
     const int lshift = logn - B::l;
@@ -239,7 +249,9 @@ __device__ __forceinline__ void fill_pass_tab(double* t, const DevPlan& p, int l
         const int cnt = 16 * PT::ns(q);
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const int k = e >> 4, r = e & 15;
-            t[PT::off(q) + k * PT::ROW + r] = p.P[tw_index<INV>(PT::expo(q, k, r), lshift, nmask)].x;
+            const double2 w = p.P[tw_index<INV>(PT::expo(q, k, r), lshift, nmask)];
+            if constexpr (std::is_same<T, double2>::value) t[PT::off(q) + k * PT::ROW + r] = w;
+            else t[PT::off(q) + k * PT::ROW + r] = w.x;
         }
     }
 }
@@ -251,7 +263,7 @@ __device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p
     using FL = FSLds<LOGN>;
     FL L;
     L.xch = lds;
-    double* t = lds + G::XCH;
+    typename FL::Entry* t = reinterpret_cast<typename FL::Entry*>(lds + FL::XCH2);
     fill_pass_tab<G::Bn, false>(t, p, LOGN);
     fill_pass_tab<G::Bn, true>(t + FL::TC, p, LOGN);
     L.colf = t;
@@ -270,16 +282,23 @@ __device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p
 }
 
 // Inter-pass twiddles of a length-L transform from its shared pass table.
-template <class W, int L>
+template <class W, int L, class T>
 struct TwTab {
-    const double* t;
+    const T* t;
     ModC M;
     __device__ __forceinline__ void operator()(double* v, int p, int, int k) const {
-        const double* b = t + PassTab<L>::off(p) + PassTab<L>::ROW * k;
+        const T* b = t + PassTab<L>::off(p) + PassTab<L>::ROW * k;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = W::mul_w(v[r], b[r], M);
+        for (int r = 0; r < 16; ++r) {
+            if constexpr (std::is_same<T, double2>::value) v[r] = W::mul_tw(v[r], b[r], M);
+            else v[r] = W::mul_w(v[r], b[r], M);
+        }
     }
 };
+template <class W, int L, class T>
+__device__ __forceinline__ TwTab<W, L, T> twtab(const T* t, const ModC& M) {
+    return TwTab<W, L, T>{t, M};
+}
 
 // Column phase, forward: length-B transforms of columns c0..c0+SC of x
 // (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
@@ -326,7 +345,7 @@ __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typena
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(in.w[i], M);
     block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
-                                                   TwTab<W, G::Bn>{L.colf, M});
+                                                   twtab<W, G::Bn>(L.colf, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i)
         st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), j * G::A + t1, B::posL(0, i) * G::A);
@@ -378,13 +397,13 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.f[i]);
     block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                  TwTab<W, G::A>{L.rowf, M});
+                                                  twtab<W, G::A>(L.rowf, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) F[i] = v[i];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.g[i]);
     block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                  TwTab<W, G::A>{L.rowf, M});
+                                                  twtab<W, G::A>(L.rowf, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
         const double gs = W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M);
@@ -393,16 +412,16 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     if (B::R0 != B::RL) {
 #pragma unroll
         for (int i = 0; i < B::E; ++i) L.xch[B::lds(s, B::posL(j, i))] = v[i];
-        __syncthreads();
+        xch_sync<B::WAVE_LOCAL>();
 #pragma unroll
         for (int i = 0; i < B::E; ++i) v[i] = L.xch[B::lds(s, B::pos0(j, i))];
-        __syncthreads();
+        xch_sync<B::WAVE_LOCAL>();
     }
     typename Tw4<W>::T tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, rowoff, B::posL(0, i));
     block_dft_tw<W, G::A, G::SR, POS_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                 TwTab<W, G::A>{L.rowi, M});
+                                                 twtab<W, G::A>(L.rowi, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i));
 }
@@ -447,7 +466,7 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.w[i]);
     block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
-                                                  TwTab<W, G::Bn>{L.coli, M});
+                                                  twtab<W, G::Bn>(L.coli, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
         const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
@@ -476,7 +495,7 @@ __device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, ty
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = ld_scr<W>(by, u2 * G::A + j, B::pos0(0, i));
     block_dft_tw<W, G::A, G::SR, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                  TwTab<W, G::A>{L.rowf, M});
+                                                  twtab<W, G::A>(L.rowf, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) st_word<W>(bx, W::canon(v[i], M), u2 + G::Bn * j, G::Bn * B::posL(0, i));
 }
@@ -500,7 +519,7 @@ __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typ
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, u2 * G::A + j, B::posL(0, i));
     block_dft_tw<W, G::A, G::SR, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                 TwTab<W, G::A>{L.rowi, M});
+                                                 twtab<W, G::A>(L.rowi, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), u2 * G::A + j, B::posL(0, i));
 }
@@ -545,12 +564,22 @@ __global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* 
                                L);
 }
 
+// Residency of the persistent fused kernel.  Where the LDS (<= 80 KB) and
+// register (<= 128 VGPRs) budgets allow, two workgroups share a CU and hide
+// each other's memory and barrier latency; otherwise one workgroup per CU
+// issues the next block's loads before transforming the current block.
+template <class W, int LOGN>
+struct FusedCfg {
+    static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16;
+    static constexpr int MINB = TWO ? 2 : 1;
+};
+
 // Persistent fused convolution of a uniform-length batch: one workgroup owns
 // one convolution at a time, start to finish, with a private 2N-word scratch.
 template <class W, int LOGN>
-__global__ __launch_bounds__(512) void k_conv_fused(const typename W::word* f, const typename W::word* g,
-                                                    typename W::word* h, const uint64_t* __restrict__ offs,
-                                                    uint32_t count, typename W::sword* scratch, DevPlan p) {
+__global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
+    const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
+    uint32_t count, typename W::sword* scratch, DevPlan p) {
     using G = FS<LOGN>;
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
@@ -561,6 +590,16 @@ __global__ __launch_bounds__(512) void k_conv_fused(const typename W::word* f, c
         const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
         const typename W::word* fi = f + off;
         const typename W::word* gi = g + off;
+        if constexpr (FusedCfg<W, LOGN>::TWO) {
+            for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(fi, Yf, c0, p, L);
+            for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(gi, Yg, c0, p, L);
+            __syncthreads();
+            for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN>(Yf, Yg, r0, p, L);
+            __syncthreads();
+            for (int c0 = 0; c0 < G::A; c0 += G::SC) col_inv_block<W, LOGN, false>(Yf, h + off, c0, p, L);
+            __syncthreads();
+            continue;
+        }
         // columns of f then of g; the next block's loads are issued before
         // the current block is transformed
         ColIn<W, LOGN> cin = col_fwd_load<W, LOGN>(fi, 0);
