@@ -36,6 +36,7 @@ struct Caches {
     std::map<std::tuple<int, uint64_t, int, uint64_t>, Plan> plans;   // (dev, m, log2n, root)
     std::map<std::pair<int, void*>, Buf> work;                        // (dev, stream) -> scratch
     std::map<std::pair<int, void*>, Buf> flag;                        // (dev, stream) -> range flag
+    std::map<std::pair<int, void*>, Buf> queue;                       // (dev, stream) -> work queue
     std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
     std::map<uint64_t, int> moduli;                                   // m -> log2 nu or -1
     std::map<int, int> cu_count;                                      // dev -> CUs
@@ -215,6 +216,27 @@ ntt_status get_buf(std::map<std::pair<int, void*>, Buf>& pool, void* stream, siz
         b.bytes = bytes;
     }
     *out = b.ptr;
+    return NTT_OK;
+}
+
+// Per-(device, stream) work queue of the persistent kernels: two uint32 words,
+// zeroed once here; every launch leaves them zero again.
+ntt_status get_queue(void* stream, uint32_t** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
+    std::lock_guard<std::mutex> g(caches().mu);
+    Buf& b = caches().queue[std::make_pair(dev, stream)];
+    if (!b.ptr) {
+        hipError_t e = hipMalloc(&b.ptr, 256);
+        if (e == hipSuccess) e = hipMemset(b.ptr, 0, 256);
+        if (e != hipSuccess) {
+            if (b.ptr) (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+            return hip_status(e);
+        }
+        b.bytes = 256;
+    }
+    *out = (uint32_t*)b.ptr;
     return NTT_OK;
 }
 
@@ -441,8 +463,11 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
             void* ws = nullptr;
             st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
             if (st != NTT_OK) return st;
+            uint32_t* q = nullptr;
+            st = get_queue(stream, &q);
+            if (st != NTT_OK) return st;
             st = hip_status(launch_conv_fused((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs,
-                                              c, ws, (uint32_t)grid, p->dev, s));
+                                              c, ws, q, (uint32_t)grid, p->dev, s));
         }
         if (st != NTT_OK) return st;
     }
@@ -498,6 +523,8 @@ void ntt_release_caches(void) {
     c.work.clear();
     for (auto& kv : c.flag) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     c.flag.clear();
+    for (auto& kv : c.queue) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c.queue.clear();
     for (auto& kv : c.offsets) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     c.offsets.clear();
 }

@@ -574,19 +574,44 @@ struct FusedCfg {
     static constexpr int MINB = TWO ? 2 : 1;
 };
 
+// Work queue of a persistent launch: q[0] is the next item, q[1] counts the
+// workgroups that have left.  Both are zero when a launch starts; the last
+// workgroup to leave zeroes them again for the next launch on the stream.
+__device__ __forceinline__ uint32_t queue_take(uint32_t* q, uint32_t* slot) {
+    __syncthreads();   // every thread has read the previous ticket
+    if (threadIdx.x == 0) *slot = atomicAdd(&q[0], 1u);
+    __syncthreads();
+    return *slot;
+}
+__device__ __forceinline__ void queue_leave(uint32_t* q) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&q[1], 1u) == gridDim.x - 1) {
+            __threadfence();
+            atomicExch(&q[0], 0u);
+            atomicExch(&q[1], 0u);
+        }
+    }
+}
+
 // Persistent fused convolution of a uniform-length batch: one workgroup owns
-// one convolution at a time, start to finish, with a private 2N-word scratch.
+// one convolution at a time, start to finish, with a private 2N-word scratch,
+// and takes its next convolution from the work queue (workgroups that share a
+// CU do not progress at the same rate).
 template <class W, int LOGN>
 __global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
     const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
-    uint32_t count, typename W::sword* scratch, DevPlan p) {
+    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p) {
     using G = FS<LOGN>;
     __shared__ double lds[FSLds<LOGN>::WORDS];
+    __shared__ uint32_t ticket;
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     typename W::sword* Yf = scratch + (size_t)blockIdx.x * 2 * G::N;
     typename W::sword* Yg = Yf + G::N;
     constexpr int CL = G::A - G::SC;
-    for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    for (;;) {
+        const uint32_t item = queue_take(queue, &ticket);
+        if (item >= count) break;
         const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
         const typename W::word* fi = f + off;
         const typename W::word* gi = g + off;
@@ -637,6 +662,7 @@ __global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
         col_inv_compute<W, LOGN, false>(iin, h + off, CL, p, L);
         __syncthreads();
     }
+    queue_leave(queue);
 }
 
 // Sets *flag when some x[i] >= m.
@@ -798,14 +824,15 @@ hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, voi
 
 template <class W>
 static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                               uint32_t count, void* scratch, uint32_t grid, const DevPlan& p, hipStream_t st) {
+                               uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
+                               hipStream_t st) {
     using T = typename W::word;
     using SW = typename W::sword;
     switch (logn) {
 #define CASE(n)                                                                                                   \
     case n:                                                                                                       \
         hipLaunchKernelGGL((k_conv_fused<W, n>), dim3(grid), dim3(FS<n>::T), 0, st, (const T*)f, (const T*)g, (T*)h, \
-                           offs, count, (SW*)scratch, p);                                                         \
+                           offs, count, (SW*)scratch, queue, p);                                                  \
         return hipGetLastError();
         NTT_LARGE_CASES(CASE)
 #undef CASE
@@ -815,10 +842,11 @@ static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, 
 }
 
 hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, void* scratch, uint32_t grid, const DevPlan& p, hipStream_t st) {
+                             uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
+                             hipStream_t st) {
     if (count == 0) return hipSuccess;
-    return wbits == 32 ? conv_fused_t<W32>(logn, f, g, h, offs, count, scratch, grid, p, st)
-                       : conv_fused_t<W64>(logn, f, g, h, offs, count, scratch, grid, p, st);
+    return wbits == 32 ? conv_fused_t<W32>(logn, f, g, h, offs, count, scratch, queue, grid, p, st)
+                       : conv_fused_t<W64>(logn, f, g, h, offs, count, scratch, queue, grid, p, st);
 }
 
 template <class W>

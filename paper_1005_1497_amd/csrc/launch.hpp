@@ -32,9 +32,12 @@ hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* 
                                 uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st);
 hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
                                const DevPlan& p, hipStream_t st);
-// scratch: grid * 2N scratch words
+// scratch: grid * 2N scratch words; queue: two uint32 work-queue words, zero
+// before the launch and zero again after it (launches sharing a queue must be
+// ordered, e.g. on one stream)
 hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, void* scratch, uint32_t grid, const DevPlan& p, hipStream_t st);
+                             uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
+                             hipStream_t st);
 int fused_blocks_per_cu(int wbits, int logn);
 int fused_threads(int logn);
 hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st);
