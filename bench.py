@@ -180,6 +180,30 @@ def main():
         torch.cuda.synchronize()
         forms["per_item_ms_per_step"] = (time.perf_counter() - t1) * 1e3
         forms["per_item_conv_per_s"] = COUNT / (forms["per_item_ms_per_step"] / 1e3)
+        # the same fused launch captured once in a HIP graph and replayed
+        gs = torch.cuda.Stream()
+        nt.conv_batched(f, g, desc, m, out=h, stream=gs)     # plans and workspaces of the capture stream
+        gs.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            nt.conv_batched(f, g, desc, m, out=h, stream=gs)
+        torch.cuda.synchronize()
+        greps = max(args.steps, 5)
+        gevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(greps)]
+        with torch.cuda.stream(gs):                          # replay() launches on the current stream
+            for a, b in gevs:
+                a.record(gs)
+                graph.replay()
+                b.record(gs)
+        torch.cuda.synchronize()
+        gper = np.array([a.elapsed_time(b) for a, b in gevs])
+        forms["graph_replay_ms_per_step"] = float(gper.mean())
+        forms["graph_replay_conv_per_s"] = COUNT / (gper.mean() / 1e3)
+        gok = bool(np.array_equal(h.cpu().numpy().view(np.uint32), hh))
+        forms["graph_replay_matches_eager"] = gok
+        if not gok:
+            log("graph replay output differs from the eager output")
+        del graph
 
     value = COUNT * args.steps / wall
     ms = wall / args.steps * 1e3

@@ -13,6 +13,7 @@
 // on each row, and the last phase runs the inverse column transforms.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "blockdft.hpp"
@@ -864,7 +865,24 @@ static int fused_bpc_t(int logn) {
     return e == hipSuccess ? nb : 0;
 }
 
-int fused_blocks_per_cu(int wbits, int logn) { return wbits == 32 ? fused_bpc_t<W32>(logn) : fused_bpc_t<W64>(logn); }
+// Occupancy of the fused kernel, queried once per (word width, length) so that
+// later calls (also under graph capture) make no runtime query.
+int fused_blocks_per_cu(int wbits, int logn) {
+    // thread-safe one-time initialisation of the table (-1: not yet queried)
+    static std::atomic<int>* cache = [] {
+        auto* c = new std::atomic<int>[2 * (MAX_LOG2N + 1)];
+        for (int i = 0; i < 2 * (MAX_LOG2N + 1); ++i) c[i].store(-1);
+        return c;
+    }();
+    if (logn < 0 || logn > MAX_LOG2N) return 0;
+    std::atomic<int>& c = cache[(wbits == 32 ? 0 : MAX_LOG2N + 1) + logn];
+    int v = c.load(std::memory_order_relaxed);
+    if (v < 0) {
+        v = wbits == 32 ? fused_bpc_t<W32>(logn) : fused_bpc_t<W64>(logn);
+        c.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
 
 int fused_threads(int logn) {
     switch (logn) {
