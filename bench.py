@@ -258,8 +258,8 @@ def _time_ms(fn, reps, stream):
 
 def uneven_bench(args):
     """10000 convolutions of lengths 2^n, n uniform in [6, 19], m = 13631489,
-    packed back to back: one conv_batched call (one launch per length class)
-    against one launch sequence per item."""
+    packed back to back: one conv_batched call as a single persistent launch,
+    against one launch per length class and one launch sequence per item."""
     import torch
     import paper_1005_1497_amd as nt
     import seeded_inputs as si
@@ -276,15 +276,24 @@ def uneven_bench(args):
         run()
     torch.cuda.synchronize()
     per = _time_ms(run, args.steps, st)
+    ref = h.cpu()
+    run(nt.FLAG_PER_CLASS)
+    torch.cuda.synchronize()
+    per_class = _time_ms(lambda: run(nt.FLAG_PER_CLASS), args.steps, st)
+    same_class = bool(torch.equal(h.cpu(), ref))
     run(nt.FLAG_PER_ITEM)
     torch.cuda.synchronize()
     per_item = _time_ms(lambda: run(nt.FLAG_PER_ITEM), 2, st)
+    same_item = bool(torch.equal(h.cpu(), ref))
     total = w.total_elems
     out = {"metric": "exact convolutions/s, uneven batch", "value": 10000 / (per.mean() / 1e3), "unit": "conv/s",
            "ms_per_step": float(per.mean()), "elements_per_s": total / (per.mean() / 1e3),
            "hbm_gbs_algorithmic": 12 * total / (per.mean() / 1e3) / 1e9,
            "config": {"workload": w.name, "total_elements": total},
-           "forms": {"per_item_ms": float(per_item.mean()), "per_item_conv_per_s": 10000 / (per_item.mean() / 1e3)}}
+           "forms": {"single_launch_ms": float(per.mean()),
+                     "per_class_ms": float(per_class.mean()), "per_class_matches": same_class,
+                     "per_item_ms": float(per_item.mean()), "per_item_matches": same_item,
+                     "per_item_conv_per_s": 10000 / (per_item.mean() / 1e3)}}
     print(json.dumps(out), flush=True)
 
 

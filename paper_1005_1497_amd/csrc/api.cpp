@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -342,6 +343,105 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
     return hip_status(launch_ntt_fourstep((int)elem_bits, log2n, inv, x, X, batch, ws, p->dev, s));
 }
 
+// One launch for the items of one length class: the LDS kernel below 2^13,
+// the persistent fused four-step kernel above.
+ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan* p, uint32_t elem_bits,
+                        const char* F, const char* G, char* H, hipStream_t s, void* stream) {
+    const size_t wb = elem_bits / 8;
+    const uint32_t c = (uint32_t)off.size();
+    // contiguous uniform run: offsets base + i N, no table needed
+    bool contiguous = true;
+    for (uint32_t i = 1; i < c && contiguous; ++i) contiguous = off[i] == off[0] + ((uint64_t)i << n);
+    const uint64_t base = contiguous ? off[0] : 0;
+    const uint64_t* doffs = nullptr;
+    ntt_status st = NTT_OK;
+    if (!contiguous) {
+        st = get_offsets(off, &doffs);
+        if (st != NTT_OK) return st;
+    }
+    if ((int)n <= SMALL_MAX_LOG2N)
+        return hip_status(
+            launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c, p->dev, s));
+    // persistent fused form: grid = resident workgroups, bounded by a 1 GiB
+    // scratch budget (2N words per workgroup)
+    // tuning override: NTTMI_FUSED_WG_PER_CU caps resident workgroups per CU
+    int per_cu = std::max(1, fused_blocks_per_cu((int)elem_bits, n));
+    if (const char* e = std::getenv("NTTMI_FUSED_WG_PER_CU")) {
+        const int cap = std::atoi(e);
+        if (cap > 0) per_cu = std::min(per_cu, cap);
+    }
+    uint64_t grid = (uint64_t)std::max(1, cu_count()) * per_cu;
+    const uint64_t per_wg = ((uint64_t)2 * wb) << n;
+    grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));
+    grid = std::min<uint64_t>(grid, c);
+    void* ws = nullptr;
+    st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
+    if (st != NTT_OK) return st;
+    uint32_t* q = nullptr;
+    st = get_queue(stream, &q);
+    if (st != NTT_OK) return st;
+    return hip_status(launch_conv_fused((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c,
+                                        ws, q, (uint32_t)grid, p->dev, s));
+}
+
+// One persistent launch for every class of length <= 2^nmax.  The task list
+// runs longest first (each four-step item is a task; shorter items go in tiles
+// of multi_tile(n)), so the short tasks fill in behind the long ones.  The
+// item offsets, the task list and the per-length plans are uploaded once per
+// distinct batch and cached by content.
+ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
+                        std::map<uint32_t, const Plan*>& plans, uint32_t nmax, uint32_t elem_bits, const char* F,
+                        const char* G, char* H, hipStream_t s, void* stream) {
+    std::vector<uint64_t> toffs;
+    std::vector<uint64_t> tasks;   // two words per task: first item; log2n | count << 32
+    uint32_t nbig = 0;
+    for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
+        const uint32_t n = it->first;
+        if (n > nmax) continue;
+        const std::vector<uint64_t>& off = it->second;
+        const uint32_t tile = (int)n <= SMALL_MAX_LOG2N ? (uint32_t)multi_tile((int)n) : 1u;
+        if ((int)n > SMALL_MAX_LOG2N) nbig = std::max(nbig, n);
+        for (size_t i = 0; i < off.size(); i += tile) {
+            const uint32_t k = (uint32_t)std::min<size_t>(tile, off.size() - i);
+            tasks.push_back(toffs.size());
+            tasks.push_back((uint64_t)n | ((uint64_t)k << 32));
+            toffs.insert(toffs.end(), off.begin() + i, off.begin() + i + k);
+        }
+    }
+    const uint32_t ntasks = (uint32_t)(tasks.size() / 2);
+    if (ntasks == 0) return NTT_OK;
+    std::vector<uint64_t> blob(toffs);
+    const size_t task_at = blob.size();
+    blob.insert(blob.end(), tasks.begin(), tasks.end());
+    const uint64_t* dblob = nullptr;
+    ntt_status st = get_offsets(blob, &dblob);
+    if (st != NTT_OK) return st;
+    // per-length plans, indexed by log2n
+    static_assert(sizeof(DevPlan) % 8 == 0, "DevPlan is uploaded as 8-byte words");
+    std::vector<DevPlan> hp(nmax + 1);
+    std::memset((void*)hp.data(), 0, hp.size() * sizeof(DevPlan));
+    for (auto& kv : plans)
+        if (kv.first <= nmax) hp[kv.first] = kv.second->dev;
+    std::vector<uint64_t> pw(hp.size() * sizeof(DevPlan) / 8);
+    std::memcpy(pw.data(), hp.data(), pw.size() * 8);
+    const uint64_t* dplans = nullptr;
+    st = get_offsets(pw, &dplans);
+    if (st != NTT_OK) return st;
+    const size_t wb = elem_bits / 8;
+    const uint64_t scratch_words = nbig ? (2ull << nbig) : 1;
+    uint64_t grid = (uint64_t)std::max(1, cu_count()) * std::max(1, multi_blocks_per_cu((int)elem_bits));
+    grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / (scratch_words * wb)));
+    grid = std::min<uint64_t>(grid, ntasks);
+    void* ws = nullptr;
+    st = get_buf(caches().work, stream, (size_t)(grid * scratch_words * wb), &ws);
+    if (st != NTT_OK) return st;
+    uint32_t* q = nullptr;
+    st = get_queue(stream, &q);
+    if (st != NTT_OK) return st;
+    return hip_status(launch_conv_multi((int)elem_bits, F, G, H, dblob + task_at, ntasks, dblob, ws, scratch_words, q,
+                                        (uint32_t)grid, (const DevPlan*)(const void*)dplans, s));
+}
+
 }  // namespace
 
 extern "C" {
@@ -419,56 +519,37 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     // length classes
     std::map<uint32_t, std::vector<uint64_t>> cls;
     for (uint32_t i = 0; i < cnt; ++i) cls[d->log2n[i]].push_back(d->offset[i]);
-    const int cus = cu_count();
+    std::map<uint32_t, const Plan*> plans;
     for (auto& kv : cls) {
         const uint32_t n = kv.first;
-        std::vector<uint64_t>& off = kv.second;
         const uint64_t item_root = powmod64(root % m, 1ull << (root_log2order - n), m);
         const Plan* p = nullptr;
         st = get_plan(m, n, item_root, lnu, &p);
         if (st != NTT_OK) return st;
-        if (flags & NTT_FLAG_PER_ITEM) {
-            for (uint64_t o : off) {
-                st = conv_one(p, elem_bits, n, F + o * wb, G + o * wb, H + o * wb, stream);
+        plans[n] = p;
+    }
+    if (flags & NTT_FLAG_PER_ITEM) {
+        for (auto& kv : cls)
+            for (uint64_t o : kv.second) {
+                st = conv_one(plans[kv.first], elem_bits, kv.first, F + o * wb, G + o * wb, H + o * wb, stream);
                 if (st != NTT_OK) return st;
             }
-            continue;
-        }
-        const uint32_t c = (uint32_t)off.size();
-        // contiguous uniform run: offsets base + i N, no table needed
-        bool contiguous = true;
-        for (uint32_t i = 1; i < c && contiguous; ++i) contiguous = off[i] == off[0] + ((uint64_t)i << n);
-        const uint64_t base = contiguous ? off[0] : 0;
-        const uint64_t* doffs = nullptr;
-        if (!contiguous) {
-            st = get_offsets(off, &doffs);
-            if (st != NTT_OK) return st;
-        }
-        if ((int)n <= SMALL_MAX_LOG2N) {
-            st = hip_status(
-                launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c, p->dev, s));
-        } else {
-            // persistent fused form: grid = resident workgroups, bounded by a
-            // 1 GiB scratch budget (2N words per workgroup)
-            // tuning override: NTTMI_FUSED_WG_PER_CU caps resident workgroups per CU
-            int per_cu = std::max(1, fused_blocks_per_cu((int)elem_bits, n));
-            if (const char* e = std::getenv("NTTMI_FUSED_WG_PER_CU")) {
-                const int cap = std::atoi(e);
-                if (cap > 0) per_cu = std::min(per_cu, cap);
-            }
-            uint64_t grid = (uint64_t)std::max(1, cus) * per_cu;
-            const uint64_t per_wg = ((uint64_t)2 * wb) << n;
-            grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));
-            grid = std::min<uint64_t>(grid, c);
-            void* ws = nullptr;
-            st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
-            if (st != NTT_OK) return st;
-            uint32_t* q = nullptr;
-            st = get_queue(stream, &q);
-            if (st != NTT_OK) return st;
-            st = hip_status(launch_conv_fused((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs,
-                                              c, ws, q, (uint32_t)grid, p->dev, s));
-        }
+        return NTT_OK;
+    }
+    // one persistent launch for every length it covers, unless the batch has
+    // a single length (whose own kernel may run two workgroups per CU) or the
+    // caller asks for one launch per length
+    const uint32_t nmax = (uint32_t)multi_max_log2n((int)elem_bits);
+    size_t multi_classes = 0;
+    for (auto& kv : cls) multi_classes += kv.first <= nmax ? 1 : 0;
+    const bool multi = !(flags & NTT_FLAG_PER_CLASS) && multi_classes >= 2;
+    if (multi) {
+        st = launch_multi(cls, plans, nmax, elem_bits, F, G, H, s, stream);
+        if (st != NTT_OK) return st;
+    }
+    for (auto& kv : cls) {
+        if (multi && kv.first <= nmax) continue;
+        st = launch_class(kv.first, kv.second, plans[kv.first], elem_bits, F, G, H, s, stream);
         if (st != NTT_OK) return st;
     }
     return NTT_OK;

@@ -25,29 +25,39 @@ namespace nttmi {
 // more workgroups per CU for latency hiding across barriers.
 #define NTT_OCC __attribute__((amdgpu_waves_per_eu(4, 8)))
 
+// Length cases of the launchers: log2 N handled in LDS, and by the four-step path.
+#define NTT_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+#define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
+
 // ------------------------------------------------------------------ small N
 constexpr int small_s(int L) { return L < 16 ? 256 : 4096 / L; }
 
-template <class W, int L>
-__global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, const typename W::word* g,
-                                                    typename W::word* h, const uint64_t* __restrict__ offs,
-                                                    uint32_t count, DevPlan p) {
-    constexpr int S = small_s(L);
+// One tile of S convolutions of length L <= 2^12, entirely in the LDS of one
+// workgroup of S * max(1, L/16) threads: forward(f), forward(g), the product
+// with N^-1 folded in, inverse and the canonical store.  Item s of the tile
+// starts at offs[s] (offs != null) or at base + s L; items s >= cnt are
+// computed on item 0's data and not stored.
+template <class W, int L, int S>
+__device__ __forceinline__ void small_conv_tile(const typename W::word* f, const typename W::word* g,
+                                                typename W::word* h, const uint64_t* offs, uint64_t base,
+                                                uint32_t cnt, const DevPlan& p, double* lds, int tid) {
     using B = Blk<L, S, POS_FAST>;
-    __shared__ double lds[B::LDS_DOUBLES];
     int s, j;
-    B::item(threadIdx.x, s, j);
-    const uint64_t item = (uint64_t)blockIdx.x * S + s;
-    const bool valid = item < count;
-    const uint64_t off = valid ? (offs ? offs[item] : item * (uint64_t)L) : (offs ? offs[0] : 0);
+    B::item(tid, s, j);
+    const bool valid = (uint32_t)s < cnt;
+    const uint32_t si = valid ? (uint32_t)s : 0u;
+    const uint64_t off = offs ? offs[si] : base + (uint64_t)si * L;
     const ModC M = p.M;
     const int lshift = p.logn - B::l;
-    double F[B::E], v[B::E];
+    // the forward transform of f waits in scratch words (|F| <= 8m + 32 fits
+    // an int32 for 32-bit words), which halves its registers
+    typename W::sword F[B::E];
+    double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(f[off + B::pos0(j, i)], M);
     block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) F[i] = v[i];
+    for (int i = 0; i < B::E; ++i) F[i] = W::to_s(v[i]);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(g[off + B::pos0(j, i)], M);
     block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
@@ -55,7 +65,7 @@ __global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, c
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
         const double gs = W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M);
-        v[i] = W::mul_var(F[i], gs, M);
+        v[i] = W::mul_var(W::from_s(F[i]), gs, M);
     }
     if (B::R0 != B::RL) {
         // output positions of the forward transform differ from the input
@@ -72,6 +82,17 @@ __global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, c
 #pragma unroll
         for (int i = 0; i < B::E; ++i) h[off + B::posL(j, i)] = W::canon(v[i], M);
     }
+}
+
+template <class W, int L>
+__global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, const typename W::word* g,
+                                                    typename W::word* h, const uint64_t* __restrict__ offs,
+                                                    uint32_t count, DevPlan p) {
+    constexpr int S = small_s(L);
+    __shared__ double lds[Blk<L, S, POS_FAST>::LDS_DOUBLES];
+    const uint64_t first = (uint64_t)blockIdx.x * S;
+    const uint32_t cnt = (uint32_t)(count - first < (uint64_t)S ? count - first : (uint64_t)S);
+    small_conv_tile<W, L, S>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds, threadIdx.x);
 }
 
 template <class W, int L, bool INV>
@@ -257,28 +278,39 @@ __device__ __forceinline__ void fill_pass_tab(T* t, const DevPlan& p, int logn) 
     }
 }
 
-// Fills the twiddle tables; ends with a barrier.
+// Where the exchange buffer and the twiddle tables sit in `lds`.
 template <int LOGN>
-__device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p) {
-    using G = FS<LOGN>;
+__device__ __forceinline__ FSLds<LOGN> fs_lds_layout(double* lds) {
     using FL = FSLds<LOGN>;
     FL L;
     L.xch = lds;
     typename FL::Entry* t = reinterpret_cast<typename FL::Entry*>(lds + FL::XCH2);
-    fill_pass_tab<G::Bn, false>(t, p, LOGN);
-    fill_pass_tab<G::Bn, true>(t + FL::TC, p, LOGN);
     L.colf = t;
     L.coli = t + FL::TC;
-    if (FL::SAME) {
-        L.rowf = L.colf;
-        L.rowi = L.coli;
-    } else {
-        fill_pass_tab<G::A, false>(t + 2 * FL::TC, p, LOGN);
-        fill_pass_tab<G::A, true>(t + 2 * FL::TC + FL::TR, p, LOGN);
-        L.rowf = t + 2 * FL::TC;
-        L.rowi = t + 2 * FL::TC + FL::TR;
+    L.rowf = FL::SAME ? L.colf : t + 2 * FL::TC;
+    L.rowi = FL::SAME ? L.coli : t + 2 * FL::TC + FL::TR;
+    return L;
+}
+
+// Fills the twiddle tables of plan p; ends with a barrier.
+template <int LOGN>
+__device__ __forceinline__ void fs_lds_fill(const FSLds<LOGN>& L, const DevPlan& p) {
+    using G = FS<LOGN>;
+    using FL = FSLds<LOGN>;
+    using E = typename FL::Entry;
+    fill_pass_tab<G::Bn, false>(const_cast<E*>(L.colf), p, LOGN);
+    fill_pass_tab<G::Bn, true>(const_cast<E*>(L.coli), p, LOGN);
+    if (!FL::SAME) {
+        fill_pass_tab<G::A, false>(const_cast<E*>(L.rowf), p, LOGN);
+        fill_pass_tab<G::A, true>(const_cast<E*>(L.rowi), p, LOGN);
     }
     __syncthreads();
+}
+
+template <int LOGN>
+__device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p) {
+    const FSLds<LOGN> L = fs_lds_layout<LOGN>(lds);
+    fs_lds_fill<LOGN>(L, p);
     return L;
 }
 
@@ -595,39 +627,26 @@ __device__ __forceinline__ void queue_leave(uint32_t* q) {
     }
 }
 
-// Persistent fused convolution of a uniform-length batch: one workgroup owns
-// one convolution at a time, start to finish, with a private 2N-word scratch,
-// and takes its next convolution from the work queue (workgroups that share a
-// CU do not progress at the same rate).
-template <class W, int LOGN>
-__global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
-    const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
-    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p) {
+// One convolution of length 2^LOGN by the four-step path, start to finish, in
+// one workgroup: columns of f and of g into the scratch Yf, Yg (N words each),
+// rows (forward f, forward g, product with N^-1, inverse) back into Yf, then
+// the inverse columns into h.  With PREFETCH each block's loads are issued
+// before the previous block is transformed.  Ends with a barrier.
+template <class W, int LOGN, bool PREFETCH>
+__device__ __forceinline__ void fused_conv_item(const typename W::word* fi, const typename W::word* gi,
+                                                typename W::word* hi, typename W::sword* Yf,
+                                                typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN>& L) {
     using G = FS<LOGN>;
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    __shared__ uint32_t ticket;
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    typename W::sword* Yf = scratch + (size_t)blockIdx.x * 2 * G::N;
-    typename W::sword* Yg = Yf + G::N;
     constexpr int CL = G::A - G::SC;
-    for (;;) {
-        const uint32_t item = queue_take(queue, &ticket);
-        if (item >= count) break;
-        const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
-        const typename W::word* fi = f + off;
-        const typename W::word* gi = g + off;
-        if constexpr (FusedCfg<W, LOGN>::TWO) {
-            for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(fi, Yf, c0, p, L);
-            for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(gi, Yg, c0, p, L);
-            __syncthreads();
-            for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN>(Yf, Yg, r0, p, L);
-            __syncthreads();
-            for (int c0 = 0; c0 < G::A; c0 += G::SC) col_inv_block<W, LOGN, false>(Yf, h + off, c0, p, L);
-            __syncthreads();
-            continue;
-        }
-        // columns of f then of g; the next block's loads are issued before
-        // the current block is transformed
+    if constexpr (!PREFETCH) {
+        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(fi, Yf, c0, p, L);
+        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(gi, Yg, c0, p, L);
+        __syncthreads();
+        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN>(Yf, Yg, r0, p, L);
+        __syncthreads();
+        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_inv_block<W, LOGN, false>(Yf, hi, c0, p, L);
+        __syncthreads();
+    } else {
         ColIn<W, LOGN> cin = col_fwd_load<W, LOGN>(fi, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
             const ColIn<W, LOGN> nxt = col_fwd_load<W, LOGN>(fi, c0 + G::SC);
@@ -657,12 +676,122 @@ __global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
         ColInvIn<W, LOGN> iin = col_inv_load<W, LOGN>(Yf, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
             const ColInvIn<W, LOGN> nxt = col_inv_load<W, LOGN>(Yf, c0 + G::SC);
-            col_inv_compute<W, LOGN, false>(iin, h + off, c0, p, L);
+            col_inv_compute<W, LOGN, false>(iin, hi, c0, p, L);
             iin = nxt;
         }
-        col_inv_compute<W, LOGN, false>(iin, h + off, CL, p, L);
+        col_inv_compute<W, LOGN, false>(iin, hi, CL, p, L);
         __syncthreads();
     }
+}
+
+// Persistent fused convolution of a uniform-length batch: one workgroup owns
+// one convolution at a time, start to finish, with a private 2N-word scratch,
+// and takes its next convolution from the work queue (workgroups that share a
+// CU do not progress at the same rate).
+template <class W, int LOGN>
+__global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
+    const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
+    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p) {
+    using G = FS<LOGN>;
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    __shared__ uint32_t ticket;
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    typename W::sword* Yf = scratch + (size_t)blockIdx.x * 2 * G::N;
+    typename W::sword* Yg = Yf + G::N;
+    for (;;) {
+        const uint32_t item = queue_take(queue, &ticket);
+        if (item >= count) break;
+        const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
+        fused_conv_item<W, LOGN, !FusedCfg<W, LOGN>::TWO>(f + off, g + off, h + off, Yf, Yg, p, L);
+    }
+    queue_leave(queue);
+}
+
+// ------------------------------------------------------------------ one launch, many lengths
+// Persistent convolution of a batch of uneven lengths 2^0 .. 2^NMAX in one
+// launch.  The host lists tasks longest first: one task per convolution of
+// length > 2^12 (the fused four-step path of fused_conv_item), one tile of up to
+// multi_s(L) convolutions per task below (small_conv_tile).  Workgroups take
+// tasks from the work queue, so the short tasks at the end of the list fill in
+// behind the long ones.  plans[n] is the plan of length 2^n.
+struct MultiTask {
+    uint64_t first;   // index of the task's first item in the item-offset list
+    uint32_t logn;
+    uint32_t cnt;     // items in the task (1 above 2^12)
+};
+constexpr int multi_s(int L) { return L < 16 ? 512 : 8192 / L; }
+template <class W>
+struct MultiCfg {
+    static constexpr int NMAX = (W::WB == 4) ? 19 : 18;
+    static constexpr int mx(int a, int b) { return a > b ? a : b; }
+    template <int N>
+    static constexpr int large_words() {
+        if constexpr (N < 13) return 1;
+        else return mx(FSLds<N>::WORDS, large_words<N - 1>());
+    }
+    static constexpr int SMALL_WORDS = 8704;   // Blk<L, 8192/L, POS_FAST>::LDS_DOUBLES for 16 < L <= 4096
+    static constexpr int WORDS = mx(large_words<NMAX>(), SMALL_WORDS);
+};
+
+// Tasks of length 2^K, while the queue hands them out: the task list is
+// sorted longest first and tickets only grow, so a workgroup meets every
+// length at most once and in decreasing order.  Each length has its own loop
+// (no loop around all of them), so what the compiler hoists out of one
+// length's loop stays inside that length's code.  Returns the first ticket of
+// a shorter length (or past the end).
+template <class W, int K>
+__device__ __forceinline__ uint32_t multi_run(uint32_t t, const typename W::word* f, const typename W::word* g,
+                                              typename W::word* h, const MultiTask* __restrict__ tasks,
+                                              uint32_t ntasks, const uint64_t* __restrict__ toffs,
+                                              typename W::sword* Y, uint32_t* queue,
+                                              const DevPlan* __restrict__ plans, double* lds, uint32_t* ticket) {
+    if (t >= ntasks || tasks[t].logn != (uint32_t)K) return t;
+    const DevPlan p = plans[K];
+    if constexpr (K > SMALL_MAX_LOG2N) {
+        const FSLds<K> L = fs_lds_layout<K>(lds);
+        fs_lds_fill<K>(L, p);
+        do {
+            const uint64_t o = toffs[tasks[t].first];
+            fused_conv_item<W, K, true>(f + o, g + o, h + o, Y, Y + (1 << K), p, L);
+            t = __builtin_amdgcn_readfirstlane(queue_take(queue, ticket));
+        } while (t < ntasks && tasks[t].logn == (uint32_t)K);
+    } else {
+        do {
+            const MultiTask task = tasks[t];
+            // the thread index, opaque to the compiler on every pass, so that the
+            // tile's per-thread addressing is recomputed here instead of being
+            // held in registers across the whole loop
+            int tid = (int)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            small_conv_tile<W, 1 << K, multi_s(1 << K)>(f, g, h, toffs + task.first, 0, task.cnt, p, lds, tid);
+            t = __builtin_amdgcn_readfirstlane(queue_take(queue, ticket));
+        } while (t < ntasks && tasks[t].logn == (uint32_t)K);
+    }
+    return t;
+}
+
+template <class W, int K>
+__device__ __forceinline__ uint32_t multi_from(uint32_t t, const typename W::word* f, const typename W::word* g,
+                                               typename W::word* h, const MultiTask* __restrict__ tasks,
+                                               uint32_t ntasks, const uint64_t* __restrict__ toffs,
+                                               typename W::sword* Y, uint32_t* queue,
+                                               const DevPlan* __restrict__ plans, double* lds, uint32_t* ticket) {
+    t = multi_run<W, K>(t, f, g, h, tasks, ntasks, toffs, Y, queue, plans, lds, ticket);
+    if constexpr (K > 0) return multi_from<W, K - 1>(t, f, g, h, tasks, ntasks, toffs, Y, queue, plans, lds, ticket);
+    else return t;
+}
+
+template <class W>
+__global__ __launch_bounds__(512, 1) void k_conv_multi(const typename W::word* f, const typename W::word* g,
+                                                       typename W::word* h, const MultiTask* __restrict__ tasks,
+                                                       uint32_t ntasks, const uint64_t* __restrict__ toffs,
+                                                       typename W::sword* scratch, uint64_t scratch_words,
+                                                       uint32_t* queue, const DevPlan* __restrict__ plans) {
+    __shared__ double lds[MultiCfg<W>::WORDS];
+    __shared__ uint32_t ticket;
+    typename W::sword* Y = scratch + (size_t)blockIdx.x * scratch_words;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(queue_take(queue, &ticket));
+    multi_from<W, MultiCfg<W>::NMAX>(t, f, g, h, tasks, ntasks, toffs, Y, queue, plans, lds, &ticket);
     queue_leave(queue);
 }
 
@@ -691,8 +820,6 @@ hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, 
 }
 
 // ------------------------------------------------------------------ launchers
-#define NTT_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
-#define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
 
 template <class W>
 static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
@@ -840,6 +967,42 @@ static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, 
         default:
             return hipErrorInvalidValue;
     }
+}
+
+template <class W>
+static hipError_t conv_multi_t(const void* f, const void* g, void* h, const void* tasks, uint32_t ntasks,
+                               const uint64_t* toffs, void* scratch, uint64_t scratch_words, uint32_t* queue,
+                               uint32_t grid, const DevPlan* plans, hipStream_t st) {
+    using T = typename W::word;
+    hipLaunchKernelGGL(k_conv_multi<W>, dim3(grid), dim3(512), 0, st, (const T*)f, (const T*)g, (T*)h,
+                       (const MultiTask*)tasks, ntasks, toffs, (typename W::sword*)scratch, scratch_words, queue,
+                       plans);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_multi(int wbits, const void* f, const void* g, void* h, const void* tasks, uint32_t ntasks,
+                             const uint64_t* toffs, void* scratch, uint64_t scratch_words, uint32_t* queue,
+                             uint32_t grid, const DevPlan* plans, hipStream_t st) {
+    if (ntasks == 0) return hipSuccess;
+    return wbits == 32 ? conv_multi_t<W32>(f, g, h, tasks, ntasks, toffs, scratch, scratch_words, queue, grid, plans, st)
+                       : conv_multi_t<W64>(f, g, h, tasks, ntasks, toffs, scratch, scratch_words, queue, grid, plans, st);
+}
+
+int multi_max_log2n(int wbits) { return wbits == 32 ? MultiCfg<W32>::NMAX : MultiCfg<W64>::NMAX; }
+int multi_tile(int logn) { return multi_s(1 << logn); }
+int multi_blocks_per_cu(int wbits) {
+    static std::atomic<int> cache[2] = {{-1}, {-1}};
+    std::atomic<int>& c = cache[wbits == 32 ? 0 : 1];
+    int v = c.load(std::memory_order_relaxed);
+    if (v < 0) {
+        int nb = 0;
+        const hipError_t e = wbits == 32
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_multi<W32>, 512, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_multi<W64>, 512, 0);
+        v = e == hipSuccess ? nb : 0;
+        c.store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,

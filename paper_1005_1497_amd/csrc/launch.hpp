@@ -39,6 +39,17 @@ hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, 
                              uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
                              hipStream_t st);
 int fused_blocks_per_cu(int wbits, int logn);
+// One launch for a batch of uneven lengths <= 2^multi_max_log2n(wbits).  tasks:
+// device array of {uint64 first item; uint32 log2n; uint32 item count} listed
+// longest first; toffs: device item offsets in task order; plans: device array
+// of DevPlan indexed by log2n; scratch: grid * scratch_words scratch words
+// (2N words for the longest length above 2^12).
+hipError_t launch_conv_multi(int wbits, const void* f, const void* g, void* h, const void* tasks, uint32_t ntasks,
+                             const uint64_t* toffs, void* scratch, uint64_t scratch_words, uint32_t* queue,
+                             uint32_t grid, const DevPlan* plans, hipStream_t st);
+int multi_max_log2n(int wbits);
+int multi_tile(int logn);            // convolutions per task below 2^(SMALL_MAX_LOG2N + 1)
+int multi_blocks_per_cu(int wbits);
 int fused_threads(int logn);
 hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st);
 

@@ -87,3 +87,42 @@ def test_overlapping_items_rejected(nt):
     with pytest.raises(nt.NttError) as e:
         nt.conv_batched(f, f, nt.BatchDesc([10, 10], [0, 512]), M)
     assert e.value.name == "NTT_E_ARG"
+
+
+def _forms_agree(nt, lengths, seed, m=M, words=32):
+    offs = si.offsets(lengths)
+    w = si.Workload("forms", m, tuple(lengths), words, m, seed)
+    f, g = si.operands(w)
+    desc = nt.BatchDesc(lengths, offs)
+    one = host(nt.conv_batched(dev(f), dev(g), desc, m))                       # one launch
+    per_class = host(nt.conv_batched(dev(f), dev(g), desc, m, flags=nt.FLAG_PER_CLASS))
+    per_item = host(nt.conv_batched(dev(f), dev(g), desc, m, flags=nt.FLAG_PER_ITEM))
+    assert np.array_equal(one, per_class)
+    assert np.array_equal(one, per_item)
+    return f, g, offs, one
+
+
+def test_single_launch_every_length(nt):
+    # every length 2^0 .. 2^19 once, some twice, ragged tiles of the short
+    # lengths; the single persistent launch equals the per-class and per-item
+    # forms, and the oracle on each item (direct sum up to 2^10, sampled above)
+    lengths = list(range(20)) + [19, 13, 12, 12, 12, 7, 0] + [6] * 130
+    f, g, offs, h = _forms_agree(nt, lengths, 31)
+    rng = np.random.default_rng(5)
+    for n, o in zip(lengths, offs):
+        N, o = 1 << n, int(o)
+        fi, gi = f[o:o + N], g[o:o + N]
+        if n <= 10:
+            assert np.array_equal(h[o:o + N], oracle.conv_direct(fi, gi, M).astype(np.uint32)), n
+        else:
+            idx = rng.integers(0, N, 6)
+            assert np.array_equal(h[o + idx], oracle.conv_entries(fi, gi, M, idx).astype(np.uint32)), n
+
+
+def test_single_launch_reused_and_reordered(nt):
+    # the same lengths in another order, twice in a row on one stream (the
+    # work queue re-arms itself), and a batch whose longest item is short
+    lengths = [12, 16, 3, 16, 14, 9, 15, 13, 12, 3]
+    for _ in range(2):
+        _forms_agree(nt, lengths, 32)
+    _forms_agree(nt, [12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1, 0] * 3, 33)

@@ -96,3 +96,23 @@ def test_u64_uniform_batch_fused(nt):
     for i in (0, 17, count - 1):
         idx = np.array([0, 5, N - 1])
         assert np.array_equal(h[i * N + idx], oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], M, idx))
+
+
+def test_u64_single_launch_with_longer_class(nt):
+    # 64-bit words with m = 13631489 (nu = 2^19): lengths up to 2^18 go into
+    # the single persistent launch, 2^19 gets its own launch
+    m = 13631489
+    lengths = [19, 18, 5, 16, 12, 13, 9, 19, 1]
+    offs = si.offsets(lengths)
+    w = si.Workload("u64mix", m, tuple(lengths), 64, m, 41)
+    f, g = si.operands(w)
+    desc = nt.BatchDesc(lengths, offs)
+    one = host(nt.conv_batched(dev(f), dev(g), desc, m))
+    per_item = host(nt.conv_batched(dev(f), dev(g), desc, m, flags=nt.FLAG_PER_ITEM))
+    assert np.array_equal(one, per_item)
+    rng = np.random.default_rng(9)
+    for n, o in zip(lengths, offs):
+        N, o = 1 << n, int(o)
+        idx = rng.integers(0, N, 4)
+        ref = oracle.conv_entries(f[o:o + N], g[o:o + N], m, idx)
+        assert np.array_equal(one[o + idx], ref.astype(np.uint64)), n
