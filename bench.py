@@ -285,6 +285,10 @@ def uneven_bench(args):
     torch.cuda.synchronize()
     per_item = _time_ms(lambda: run(nt.FLAG_PER_ITEM), 2, st)
     same_item = bool(torch.equal(h.cpu(), ref))
+    run(nt.FLAG_AUTOTUNE)                 # tunes this batch shape once, then cached
+    torch.cuda.synchronize()
+    tuned = _time_ms(run, args.steps, st)
+    same_tuned = bool(torch.equal(h.cpu(), ref))
     total = w.total_elems
     out = {"metric": "exact convolutions/s, uneven batch", "value": 10000 / (per.mean() / 1e3), "unit": "conv/s",
            "ms_per_step": float(per.mean()), "elements_per_s": total / (per.mean() / 1e3),
@@ -292,6 +296,7 @@ def uneven_bench(args):
            "config": {"workload": w.name, "total_elements": total},
            "forms": {"single_launch_ms": float(per.mean()),
                      "per_class_ms": float(per_class.mean()), "per_class_matches": same_class,
+                     "autotuned_ms": float(tuned.mean()), "autotuned_matches": same_tuned,
                      "per_item_ms": float(per_item.mean()), "per_item_matches": same_item,
                      "per_item_conv_per_s": 10000 / (per_item.mean() / 1e3)}}
     print(json.dumps(out), flush=True)

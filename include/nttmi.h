@@ -57,6 +57,16 @@ typedef enum {
                                         (the unfused reference form) */
 #define NTT_FLAG_PER_CLASS     0x4u  /* conv_batched: one launch per length class
                                         instead of one persistent launch */
+#define NTT_FLAG_AUTOTUNE      0x8u  /* conv_batched: time the candidate forms of this
+                                        batch (one persistent launch or one launch per
+                                        length; per length: LDS tile of 256 threads or
+                                        of one wave, fused kernel at full or one-per-CU
+                                        occupancy, or the unfused four-step launches),
+                                        keep the fastest for every later batch of the
+                                        same shape (lengths, item counts rounded down to
+                                        powers of two, m, word width, device), and run
+                                        it.  Synchronises the stream; not for use while
+                                        the stream is being captured into a graph */
 
 /* Batch of independent convolutions of uneven power-of-two lengths.
  * Item i has length N_i = 2^log2n[i] and occupies elements
@@ -99,7 +109,13 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
  * 2^root_log2order; item i uses root^(2^(root_log2order - log2n[i])), of
  * exact order N_i, so log2n[i] <= root_log2order is required.  The usual choice
  * is root = 2 and root_log2order = log2(ord_m(2)).  Default form: one fused
- * forward/pointwise/inverse launch for the whole batch. */
+ * forward/pointwise/inverse persistent launch for every length up to 2^19
+ * (32-bit words) or 2^18 (64-bit words), longer lengths one launch each; a
+ * batch of a single length runs that length's own persistent kernel.  A form
+ * tuned with NTT_FLAG_AUTOTUNE for the batch's shape replaces the default.
+ * Every form gives the same result.  Once the call has run on a stream (its
+ * plans, workspaces and any tuning in place) it is capturable into a HIP graph
+ * on that stream; the captured kernels keep the workspaces of that stream. */
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc *d, const void *f, const void *g, void *h,
                         uint32_t flags, void *stream);

@@ -23,7 +23,7 @@ import torch
 __all__ = [
     "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched",
     "default_root", "modulus_order", "release_caches", "status_string",
-    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "STATUS",
+    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "STATUS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +36,7 @@ STATUS = {
 FLAG_CHECK_RANGE = 0x1
 FLAG_PER_ITEM = 0x2
 FLAG_PER_CLASS = 0x4
+FLAG_AUTOTUNE = 0x8
 
 EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "ntt_default_root",
            "ntt_modulus_order", "ntt_status_string", "ntt_release_caches")

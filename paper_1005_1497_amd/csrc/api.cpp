@@ -32,12 +32,28 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// How conv_batched runs a batch: one persistent launch for the lengths it
+// covers (multi) or one launch per length, and the form of each length's
+// launch (ClassForm).  Chosen by the autotuner and cached per batch shape.
+enum ClassForm : uint8_t {
+    CF_DEFAULT = 0,      // LDS kernel of 256 threads / persistent fused kernel at full occupancy
+    CF_SMALL_WAVE = 1,   // LDS kernel with one wave per workgroup
+    CF_FUSED_ONE = 2,    // persistent fused kernel, one workgroup per CU
+    CF_FOURSTEP = 3,     // unfused four-step: column, row and column launches over all items
+};
+struct BatchForm {
+    bool multi = false;
+    std::map<uint32_t, uint8_t> cls;   // log2n -> ClassForm
+};
+
 struct Caches {
     std::mutex mu;
     std::map<std::tuple<int, uint64_t, int, uint64_t>, Plan> plans;   // (dev, m, log2n, root)
     std::map<std::pair<int, void*>, Buf> work;                        // (dev, stream) -> scratch
     std::map<std::pair<int, void*>, Buf> flag;                        // (dev, stream) -> range flag
     std::map<std::pair<int, void*>, Buf> queue;                       // (dev, stream) -> work queue
+    std::map<std::pair<int, void*>, Buf> tune;                        // (dev, stream) -> autotuning output
+    std::map<std::vector<uint64_t>, struct BatchForm> forms;          // batch shape -> tuned form
     std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
     std::map<uint64_t, int> moduli;                                   // m -> log2 nu or -1
     std::map<int, int> cu_count;                                      // dev -> CUs
@@ -346,7 +362,8 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
 // One launch for the items of one length class: the LDS kernel below 2^13,
 // the persistent fused four-step kernel above.
 ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan* p, uint32_t elem_bits,
-                        const char* F, const char* G, char* H, hipStream_t s, void* stream) {
+                        const char* F, const char* G, char* H, hipStream_t s, void* stream,
+                        uint8_t form = CF_DEFAULT) {
     const size_t wb = elem_bits / 8;
     const uint32_t c = (uint32_t)off.size();
     // contiguous uniform run: offsets base + i N, no table needed
@@ -360,12 +377,19 @@ ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan
         if (st != NTT_OK) return st;
     }
     if ((int)n <= SMALL_MAX_LOG2N)
-        return hip_status(
-            launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c, p->dev, s));
+        return hip_status(launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c,
+                                            p->dev, s, form == CF_SMALL_WAVE ? SMALL_TILE_WAVE : SMALL_TILE_256));
+    if (form == CF_FOURSTEP && contiguous && (((uint64_t)2 * c * wb) << n) <= (1ull << 30)) {
+        void* ws = nullptr;
+        st = get_buf(caches().work, stream, (size_t)(((uint64_t)2 * c * wb) << n), &ws);
+        if (st != NTT_OK) return st;
+        return hip_status(launch_conv_fourstep((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, c,
+                                               1ull << n, ws, p->dev, s));
+    }
     // persistent fused form: grid = resident workgroups, bounded by a 1 GiB
     // scratch budget (2N words per workgroup)
     // tuning override: NTTMI_FUSED_WG_PER_CU caps resident workgroups per CU
-    int per_cu = std::max(1, fused_blocks_per_cu((int)elem_bits, n));
+    int per_cu = form == CF_FUSED_ONE ? 1 : std::max(1, fused_blocks_per_cu((int)elem_bits, n));
     if (const char* e = std::getenv("NTTMI_FUSED_WG_PER_CU")) {
         const int cap = std::atoi(e);
         if (cap > 0) per_cu = std::min(per_cu, cap);
@@ -440,6 +464,133 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
     if (st != NTT_OK) return st;
     return hip_status(launch_conv_multi((int)elem_bits, F, G, H, dblob + task_at, ntasks, dblob, ws, scratch_words, q,
                                         (uint32_t)grid, (const DevPlan*)(const void*)dplans, s));
+}
+
+// Runs a batch in the given form.
+ntt_status run_batch(const BatchForm& form, const std::map<uint32_t, std::vector<uint64_t>>& cls,
+                     std::map<uint32_t, const Plan*>& plans, uint32_t nmax, uint32_t elem_bits, const char* F,
+                     const char* G, char* H, hipStream_t s, void* stream) {
+    ntt_status st = NTT_OK;
+    if (form.multi) {
+        st = launch_multi(cls, plans, nmax, elem_bits, F, G, H, s, stream);
+        if (st != NTT_OK) return st;
+    }
+    for (auto& kv : cls) {
+        if (form.multi && kv.first <= nmax) continue;
+        auto it = form.cls.find(kv.first);
+        const uint8_t cf = it == form.cls.end() ? (uint8_t)CF_DEFAULT : it->second;
+        st = launch_class(kv.first, kv.second, plans[kv.first], elem_bits, F, G, H, s, stream, cf);
+        if (st != NTT_OK) return st;
+    }
+    return NTT_OK;
+}
+
+// Batch shape: modulus, word width, and per length the item count rounded
+// down to a power of two.
+std::vector<uint64_t> shape_key(uint64_t m, uint32_t elem_bits, const std::map<uint32_t, std::vector<uint64_t>>& cls) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::vector<uint64_t> k{(uint64_t)dev, m, elem_bits};
+    for (auto& kv : cls) {
+        uint64_t c = kv.second.size(), b = 0;
+        while (c >>= 1) ++b;
+        k.push_back(((uint64_t)kv.first << 32) | b);
+    }
+    return k;
+}
+
+bool lookup_form(const std::vector<uint64_t>& key, BatchForm* out) {
+    std::lock_guard<std::mutex> g(caches().mu);
+    auto it = caches().forms.find(key);
+    if (it == caches().forms.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void store_form(const std::vector<uint64_t>& key, const BatchForm& f) {
+    std::lock_guard<std::mutex> g(caches().mu);
+    caches().forms[key] = f;
+}
+
+// Milliseconds of `run` on the stream: one untimed run, then the best of three.
+template <class F>
+ntt_status time_ms(hipStream_t s, F run, float* best) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return NTT_E_DEVICE;
+    }
+    ntt_status st = run();
+    *best = 3.4e38f;
+    for (int r = 0; st == NTT_OK && r < 3; ++r) {
+        hipError_t e = hipEventRecord(a, s);
+        if (e == hipSuccess) st = run();
+        if (st == NTT_OK && e == hipSuccess) e = hipEventRecord(b, s);
+        if (st == NTT_OK && e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (st == NTT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) st = hip_status(e);
+        if (st == NTT_OK) *best = std::min(*best, ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
+// The autotuner: times every candidate form of each length on this batch
+// (each length alone), keeps the fastest, then times the single persistent
+// launch against the sum of the per-length bests.  Trial outputs go to a
+// scratch buffer when h overlaps f or g, so the operands survive; the caller
+// then runs the chosen form once more for the result.
+ntt_status autotune(const std::map<uint32_t, std::vector<uint64_t>>& cls, std::map<uint32_t, const Plan*>& plans,
+                    uint32_t nmax, uint32_t elem_bits, const char* F, const char* G, char* H, uint64_t total,
+                    hipStream_t s, void* stream, BatchForm* out) {
+    const size_t wb = elem_bits / 8;
+    const size_t bytes = (size_t)total * wb;
+    char* T = H;
+    if (overlap(F, bytes, H, bytes) || overlap(G, bytes, H, bytes)) {
+        void* t = nullptr;
+        ntt_status st = get_buf(caches().tune, stream, bytes, &t);
+        if (st != NTT_OK) return st;
+        T = (char*)t;
+    }
+    BatchForm best;
+    float sum_covered = 0.f;
+    for (auto& kv : cls) {
+        const uint32_t n = kv.first;
+        std::vector<uint8_t> cand{CF_DEFAULT};
+        if ((int)n <= SMALL_MAX_LOG2N) {
+            cand.push_back(CF_SMALL_WAVE);
+        } else {
+            if (fused_blocks_per_cu((int)elem_bits, n) > 1) cand.push_back(CF_FUSED_ONE);
+            cand.push_back(CF_FOURSTEP);
+        }
+        float tbest = 3.4e38f;
+        uint8_t fbest = CF_DEFAULT;
+        for (uint8_t cf : cand) {
+            float ms = 0.f;
+            ntt_status st = time_ms(s, [&] { return launch_class(n, kv.second, plans[n], elem_bits, F, G, T, s, stream, cf); },
+                                    &ms);
+            if (st != NTT_OK) return st;
+            if (ms < tbest) {
+                tbest = ms;
+                fbest = cf;
+            }
+        }
+        best.cls[n] = fbest;
+        if (n <= nmax) sum_covered += tbest;
+    }
+    size_t covered = 0;
+    for (auto& kv : cls) covered += kv.first <= nmax ? 1 : 0;
+    best.multi = false;
+    if (covered >= 2) {
+        float ms = 0.f;
+        ntt_status st = time_ms(s, [&] { return launch_multi(cls, plans, nmax, elem_bits, F, G, T, s, stream); }, &ms);
+        if (st != NTT_OK) return st;
+        best.multi = ms < sum_covered;
+    }
+    *out = best;
+    return NTT_OK;
 }
 
 }  // namespace
@@ -536,23 +687,24 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
             }
         return NTT_OK;
     }
-    // one persistent launch for every length it covers, unless the batch has
-    // a single length (whose own kernel may run two workgroups per CU) or the
-    // caller asks for one launch per length
+    // Default form: one persistent launch for every length it covers, unless
+    // the batch has a single length (whose own kernel may run two workgroups
+    // per CU).  A tuned form for this batch shape replaces the default;
+    // NTT_FLAG_AUTOTUNE tunes one now.  NTT_FLAG_PER_CLASS forces one launch
+    // per length.
     const uint32_t nmax = (uint32_t)multi_max_log2n((int)elem_bits);
     size_t multi_classes = 0;
     for (auto& kv : cls) multi_classes += kv.first <= nmax ? 1 : 0;
-    const bool multi = !(flags & NTT_FLAG_PER_CLASS) && multi_classes >= 2;
-    if (multi) {
-        st = launch_multi(cls, plans, nmax, elem_bits, F, G, H, s, stream);
+    BatchForm form;
+    form.multi = multi_classes >= 2;
+    const std::vector<uint64_t> key = shape_key(m, elem_bits, cls);
+    if (!lookup_form(key, &form) && (flags & NTT_FLAG_AUTOTUNE)) {
+        st = autotune(cls, plans, nmax, elem_bits, F, G, H, total, s, stream, &form);
         if (st != NTT_OK) return st;
+        store_form(key, form);
     }
-    for (auto& kv : cls) {
-        if (multi && kv.first <= nmax) continue;
-        st = launch_class(kv.first, kv.second, plans[kv.first], elem_bits, F, G, H, s, stream);
-        if (st != NTT_OK) return st;
-    }
-    return NTT_OK;
+    if (flags & NTT_FLAG_PER_CLASS) form.multi = false;
+    return run_batch(form, cls, plans, nmax, elem_bits, F, G, H, s, stream);
 }
 
 ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t* root) {
@@ -606,6 +758,9 @@ void ntt_release_caches(void) {
     c.flag.clear();
     for (auto& kv : c.queue) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     c.queue.clear();
+    for (auto& kv : c.tune) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c.tune.clear();
+    c.forms.clear();
     for (auto& kv : c.offsets) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     c.offsets.clear();
 }

@@ -30,7 +30,12 @@ namespace nttmi {
 #define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
 
 // ------------------------------------------------------------------ small N
+// Convolutions per workgroup of the LDS kernels: 256 threads (small_s), or one
+// wave per tile up to L = 1024 (small_s_wave), which spreads a short batch over
+// more CUs.
 constexpr int small_s(int L) { return L < 16 ? 256 : 4096 / L; }
+constexpr int small_s_wave(int L) { return L < 16 ? 64 : (L <= 1024 ? 1024 / L : 1); }
+constexpr int small_threads(int L, int S) { return L < 16 ? S : S * (L / 16); }
 
 // One tile of S convolutions of length L <= 2^12, entirely in the LDS of one
 // workgroup of S * max(1, L/16) threads: forward(f), forward(g), the product
@@ -84,11 +89,10 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
     }
 }
 
-template <class W, int L>
+template <class W, int L, int S>
 __global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, const typename W::word* g,
                                                     typename W::word* h, const uint64_t* __restrict__ offs,
                                                     uint32_t count, DevPlan p) {
-    constexpr int S = small_s(L);
     __shared__ double lds[Blk<L, S, POS_FAST>::LDS_DOUBLES];
     const uint64_t first = (uint64_t)blockIdx.x * S;
     const uint32_t cnt = (uint32_t)(count - first < (uint64_t)S ? count - first : (uint64_t)S);
@@ -821,18 +825,24 @@ hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, 
 
 // ------------------------------------------------------------------ launchers
 
+template <class W, int L, int S>
+static hipError_t conv_small_launch(const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
+                                    const DevPlan& p, hipStream_t st) {
+    using T = typename W::word;
+    hipLaunchKernelGGL((k_conv_small<W, L, S>), dim3((count + S - 1) / S), dim3(small_threads(L, S)), 0, st,
+                       (const T*)f, (const T*)g, (T*)h, offs, count, p);
+    return hipGetLastError();
+}
+
 template <class W>
 static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
-                               const DevPlan& p, hipStream_t st) {
-    using T = typename W::word;
+                               const DevPlan& p, hipStream_t st, int tile) {
     switch (logn) {
 #define CASE(n)                                                                                                   \
-    case n: {                                                                                                     \
-        const uint32_t S = small_s(1 << n);                                                                       \
-        hipLaunchKernelGGL((k_conv_small<W, 1 << n>), dim3((count + S - 1) / S), dim3(256), 0, st, (const T*)f,      \
-                           (const T*)g, (T*)h, offs, count, p);                                                   \
-        return hipGetLastError();                                                                                 \
-    }
+    case n:                                                                                                       \
+        return tile == SMALL_TILE_WAVE                                                                            \
+                   ? conv_small_launch<W, 1 << n, small_s_wave(1 << n)>(f, g, h, offs, count, p, st)            \
+                   : conv_small_launch<W, 1 << n, small_s(1 << n)>(f, g, h, offs, count, p, st);
         NTT_SMALL_CASES(CASE)
 #undef CASE
         default:
@@ -841,10 +851,10 @@ static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, 
 }
 
 hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, const DevPlan& p, hipStream_t st) {
+                             uint32_t count, const DevPlan& p, hipStream_t st, int tile) {
     if (count == 0) return hipSuccess;
-    return wbits == 32 ? conv_small_t<W32>(logn, f, g, h, offs, count, p, st)
-                       : conv_small_t<W64>(logn, f, g, h, offs, count, p, st);
+    return wbits == 32 ? conv_small_t<W32>(logn, f, g, h, offs, count, p, st, tile)
+                       : conv_small_t<W64>(logn, f, g, h, offs, count, p, st, tile);
 }
 
 template <class W>

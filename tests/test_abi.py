@@ -110,3 +110,12 @@ def test_u64_validation(lib):
     # a 58-bit Rader prime (order of 2 is 2^28) is valid but beyond exact fp64 residues
     m58 = 231292694251438081
     assert c(m58, 10, pow(2, 2 ** 18, m58), 64, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 8
+
+
+def test_flag_values_match_header():
+    import paper_1005_1497_amd as nt
+    text = open(HEADER).read()
+    flags = dict(re.findall(r"#define\s+NTT_FLAG_(\w+)\s+(0x[0-9a-fA-F]+)u", text))
+    assert flags, "no flags in the header"
+    for name, val in flags.items():
+        assert getattr(nt, "FLAG_" + name) == int(val, 16), name

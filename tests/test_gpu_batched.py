@@ -126,3 +126,26 @@ def test_single_launch_reused_and_reordered(nt):
     for _ in range(2):
         _forms_agree(nt, lengths, 32)
     _forms_agree(nt, [12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1, 0] * 3, 33)
+
+
+@pytest.mark.parametrize("lengths", [
+    [16] * 40,                                     # one length, many items
+    [16] * 3,                                      # one length, few items
+    [5] * 50 + [10] * 9 + [12] * 3,                # short lengths only
+    list(range(6, 20)) * 3,                        # the uneven mix
+])
+def test_autotuned_form_matches(nt, lengths):
+    offs = si.offsets(lengths)
+    w = si.Workload("tune", M, tuple(lengths), 32, M, 51)
+    f, g = si.operands(w)
+    desc = nt.BatchDesc(lengths, offs)
+    ref = host(nt.conv_batched(dev(f), dev(g), desc, M, flags=nt.FLAG_PER_ITEM))
+    tuned = host(nt.conv_batched(dev(f), dev(g), desc, M, flags=nt.FLAG_AUTOTUNE))
+    assert np.array_equal(tuned, ref)
+    again = host(nt.conv_batched(dev(f), dev(g), desc, M))        # the cached form
+    assert np.array_equal(again, ref)
+    # in place (h is f), tuned afresh: the trial runs must not clobber the operands
+    nt.release_caches()
+    fd = dev(f)
+    nt.conv_batched(fd, dev(g), desc, M, out=fd, flags=nt.FLAG_AUTOTUNE)
+    assert np.array_equal(host(fd), ref)
