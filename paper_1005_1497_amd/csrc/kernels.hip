@@ -608,7 +608,9 @@ __global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* 
 template <class W, int LOGN>
 struct FusedCfg {
     static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16;
-    static constexpr int MINB = TWO ? 2 : 1;
+    // minimum waves per SIMD (the second __launch_bounds__ argument): four
+    // for two 512-thread workgroups per CU, i.e. at most 128 VGPRs
+    static constexpr int WAVES_PER_EU = TWO ? 4 : 2;
 };
 
 // Work queue of a persistent launch: q[0] is the next item, q[1] counts the
@@ -693,7 +695,7 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
 // and takes its next convolution from the work queue (workgroups that share a
 // CU do not progress at the same rate).
 template <class W, int LOGN>
-__global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::MINB)) void k_conv_fused(
+__global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::WAVES_PER_EU)) void k_conv_fused(
     const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
     uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p) {
     using G = FS<LOGN>;
@@ -786,7 +788,7 @@ __device__ __forceinline__ uint32_t multi_from(uint32_t t, const typename W::wor
 }
 
 template <class W>
-__global__ __launch_bounds__(512, 1) void k_conv_multi(const typename W::word* f, const typename W::word* g,
+__global__ __launch_bounds__(512, 2) void k_conv_multi(const typename W::word* f, const typename W::word* g,
                                                        typename W::word* h, const MultiTask* __restrict__ tasks,
                                                        uint32_t ntasks, const uint64_t* __restrict__ toffs,
                                                        typename W::sword* scratch, uint64_t scratch_words,
