@@ -67,6 +67,14 @@ typedef enum {
                                         powers of two, m, word width, device), and run
                                         it.  Synchronises the stream; not for use while
                                         the stream is being captured into a graph */
+#define NTT_FLAG_EULER         0x10u /* the Euler (Pollard) form of Sec. I, Eq. 4: any
+                                        prime m (not only those of which 2 is a
+                                        lambda-root) with N | m - 1, and a root of exact
+                                        order N that need not be a power of two
+                                        (ntt_euler_root gives one).  Lengths up to
+                                        2^v, 2^v the largest power of two dividing m - 1
+                                        (ntt_max_log2n).  conv_batched:
+                                        root_log2order <= v */
 
 /* Batch of independent convolutions of uneven power-of-two lengths.
  * Item i has length N_i = 2^log2n[i] and occupies elements
@@ -126,6 +134,15 @@ ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t *root);
 
 /* log2 of ord_m(2) for a valid modulus (Prop. 2), written to *log2_nu. */
 ntt_status ntt_modulus_order(uint64_t m, uint32_t *log2_nu);
+
+/* Euler form (NTT_FLAG_EULER): for a prime m, the largest n with 2^n | m - 1,
+ * written to *log2n (NTT_E_MODULUS when m is not prime). */
+ntt_status ntt_max_log2n(uint64_t m, uint32_t *log2n);
+
+/* Euler form: a root of exact order 2^log2n modulo the prime m (requires
+ * 2^log2n | m - 1): z^((m - 1) / 2^log2n) for the smallest quadratic
+ * non-residue z.  Writes it to *root. */
+ntt_status ntt_euler_root(uint64_t m, uint32_t log2n, uint64_t *root);
 
 /* Static description of a status code. */
 const char *ntt_status_string(ntt_status s);

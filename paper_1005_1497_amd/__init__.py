@@ -23,7 +23,8 @@ import torch
 __all__ = [
     "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched",
     "default_root", "modulus_order", "release_caches", "status_string",
-    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "STATUS",
+    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "STATUS",
+    "euler_root", "max_log2n",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,9 +38,10 @@ FLAG_CHECK_RANGE = 0x1
 FLAG_PER_ITEM = 0x2
 FLAG_PER_CLASS = 0x4
 FLAG_AUTOTUNE = 0x8
+FLAG_EULER = 0x10
 
 EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "ntt_default_root",
-           "ntt_modulus_order", "ntt_status_string", "ntt_release_caches")
+           "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches")
 
 
 class NttError(RuntimeError):
@@ -75,6 +77,10 @@ def _load():
     L.ntt_default_root.restype = I32
     L.ntt_modulus_order.argtypes = [U64, ctypes.POINTER(U32)]
     L.ntt_modulus_order.restype = I32
+    L.ntt_max_log2n.argtypes = [U64, ctypes.POINTER(U32)]
+    L.ntt_max_log2n.restype = I32
+    L.ntt_euler_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
+    L.ntt_euler_root.restype = I32
     L.ntt_status_string.argtypes = [I32]
     L.ntt_status_string.restype = ctypes.c_char_p
     L.ntt_release_caches.argtypes = []
@@ -133,13 +139,31 @@ def modulus_order(m: int) -> int:
     return int(r.value)
 
 
+def max_log2n(m: int) -> int:
+    """Euler form: the largest n with 2^n dividing m - 1 (m prime)."""
+    r = ctypes.c_uint32(0)
+    _check(lib.ntt_max_log2n(int(m), ctypes.byref(r)), "ntt_max_log2n")
+    return int(r.value)
+
+
+def euler_root(m: int, log2n: int) -> int:
+    """Euler form: a root of exact order 2^log2n modulo the prime m."""
+    r = ctypes.c_uint64(0)
+    _check(lib.ntt_euler_root(int(m), int(log2n), ctypes.byref(r)), "ntt_euler_root")
+    return int(r.value)
+
+
+def _root(m, log2n, flags):
+    return euler_root(m, log2n) if flags & FLAG_EULER else default_root(m, log2n)
+
+
 def _ntt(fn, name, x, m, root, out, flags, stream):
     bits = _words(x, "x")
     N = x.shape[-1]
     log2n = _log2(N)
     batch = x.numel() // N if x.numel() else 0
     if root is None:
-        root = default_root(m, log2n)
+        root = _root(m, log2n, flags)
     if out is None:
         out = torch.empty_like(x)
     elif _words(out, "out") != bits or out.shape != x.shape:
@@ -167,7 +191,7 @@ def conv_circular(f: torch.Tensor, g: torch.Tensor, m: int, root: int | None = N
         raise ValueError("f and g must be 1-D with the same length and word width")
     log2n = _log2(f.numel())
     if root is None:
-        root = default_root(m, log2n)
+        root = _root(m, log2n, flags)
     if out is None:
         out = torch.empty_like(f)
     elif _words(out, "out") != bits or out.shape != f.shape:

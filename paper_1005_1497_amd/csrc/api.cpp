@@ -55,7 +55,7 @@ struct Caches {
     std::map<std::pair<int, void*>, Buf> tune;                        // (dev, stream) -> autotuning output
     std::map<std::vector<uint64_t>, struct BatchForm> forms;          // batch shape -> tuned form
     std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
-    std::map<uint64_t, int> moduli;                                   // m -> log2 nu or -1
+    std::map<uint64_t, std::pair<int, int>> moduli;                   // m -> (log2 nu or -1, v2(m-1) or -1)
     std::map<int, int> cu_count;                                      // dev -> CUs
 };
 
@@ -87,25 +87,37 @@ double2 tw_pair(uint64_t w, uint64_t m) {
     return t;
 }
 
-// log2(nu) for a valid modulus (prime, order of 2 a power of two: Sec. II,
-// Prop. 2); -1 otherwise.  Cached.
-int modulus_log2nu(uint64_t m) {
+// (log2 nu, v2) of a modulus: log2 of the order of 2 when m is prime and that
+// order is a power of two (2 is a lambda-root of m: Sec. II, Prop. 2), and the
+// 2-adic valuation of m - 1 when m is prime (the longest power-of-two length
+// of the Euler form, Sec. I, Eq. 4); -1 where they do not apply.  Cached.
+std::pair<int, int> modulus_info(uint64_t m) {
     Caches& c = caches();
     {
         std::lock_guard<std::mutex> g(c.mu);
         auto it = c.moduli.find(m);
         if (it != c.moduli.end()) return it->second;
     }
-    int lnu = -1;
-    if (m >= 3 && is_prime64(m)) lnu = log2_order_of_two(m);
+    int lnu = -1, v2 = -1;
+    if (m >= 3 && is_prime64(m)) {
+        lnu = log2_order_of_two(m);
+        v2 = 0;
+        while (((m - 1) >> v2 & 1) == 0) ++v2;
+    }
     std::lock_guard<std::mutex> g(c.mu);
-    c.moduli[m] = lnu;
-    return lnu;
+    c.moduli[m] = std::make_pair(lnu, v2);
+    return std::make_pair(lnu, v2);
 }
 
-ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu) {
+int modulus_log2nu(uint64_t m) { return modulus_info(m).first; }
+
+// Checks m and the word width.  Default: the paper's moduli, primes of which 2
+// is a lambda-root; *lnu = log2 nu bounds the length.  With NTT_FLAG_EULER any
+// prime; *lnu = v2(m - 1) bounds the length.
+ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu, uint32_t flags = 0) {
     if (elem_bits != 32 && elem_bits != 64) return NTT_E_ARG;
-    *lnu = modulus_log2nu(m);
+    const std::pair<int, int> info = modulus_info(m);
+    *lnu = (flags & NTT_FLAG_EULER) ? info.second : info.first;
     if (*lnu < 0) return NTT_E_MODULUS;
     if (elem_bits == 32 && m >= (1ull << 24)) return NTT_E_MODULUS;
     if (elem_bits == 64 && m >= (1ull << 62)) return NTT_E_MODULUS;
@@ -121,8 +133,8 @@ bool root_has_order(uint64_t root, uint32_t k, uint64_t m) {
     return powmod64(r, 1ull << (k - 1), m) == m - 1;
 }
 
-ntt_status validate(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, int* lnu) {
-    ntt_status st = check_modulus(m, elem_bits, lnu);
+ntt_status validate(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, int* lnu, uint32_t flags) {
+    ntt_status st = check_modulus(m, elem_bits, lnu, flags);
     if (st != NTT_OK) return st;
     if ((int)log2n > *lnu) return NTT_E_LENGTH;
     if (!root_has_order(root, log2n, m)) return NTT_E_ROOT;
@@ -147,6 +159,9 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
     const uint64_t r = root % m;
+    // log2 of the order of 2 (or -1), looked up before the cache lock is taken:
+    // modulus_info takes the same (non-recursive) lock
+    const int l2 = modulus_log2nu(m);
     Caches& c = caches();
     std::lock_guard<std::mutex> g(c.mu);
     auto key = std::make_tuple(dev, m, (int)log2n, r);
@@ -194,8 +209,11 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
         if (p.dTTi32) (void)hipFree(p.dTTi32);
         return hip_status(he);
     }
-    // N^-1 = 2^-n = 2^(nu - n) mod m: the multiplicative inverse of N (Appendix A)
-    const uint64_t ninv = powmod64(2, (1ull << lnu) - log2n, m);
+    // N^-1 mod m, the multiplicative inverse of N (Appendix A): 2^(nu - n)
+    // when 2 has order nu = 2^lnu, else N^(m - 2) (Fermat, m prime)
+    const uint64_t ninv = (l2 >= (int)log2n) ? powmod64(2, (1ull << l2) - log2n, m)
+                                             : powmod64((1ull << log2n) % m, m - 2, m);
+    (void)lnu;
     p.dev.P = p.dP;
     p.dev.TT = p.dTT;
     p.dev.TTi = p.dTTi;
@@ -337,7 +355,7 @@ ntt_status conv_one(const Plan* p, uint32_t wbits, uint32_t log2n, const void* f
 ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* x, void* X,
                    uint32_t batch, uint32_t flags, void* stream) {
     int lnu = 0;
-    ntt_status st = validate(m, log2n, root, elem_bits, &lnu);
+    ntt_status st = validate(m, log2n, root, elem_bits, &lnu, flags);
     if (st != NTT_OK) return st;
     if (batch == 0) return NTT_OK;
     if (!x || !X) return NTT_E_ARG;
@@ -610,7 +628,7 @@ ntt_status ntt_inverse(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_
 ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* f,
                          const void* g, void* h, uint32_t flags, void* stream) {
     int lnu = 0;
-    ntt_status st = validate(m, log2n, root, elem_bits, &lnu);
+    ntt_status st = validate(m, log2n, root, elem_bits, &lnu, flags);
     if (st != NTT_OK) return st;
     if (!f || !g || !h) return NTT_E_ARG;
     const size_t bytes = ((size_t)1 << log2n) * (elem_bits / 8);
@@ -630,7 +648,7 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
                         const ntt_batch_desc* d, const void* f, const void* g, void* h, uint32_t flags,
                         void* stream) {
     int lnu = 0;
-    ntt_status st = check_modulus(m, elem_bits, &lnu);
+    ntt_status st = check_modulus(m, elem_bits, &lnu, flags);
     if (st != NTT_OK) return st;
     if (!d) return NTT_E_ARG;
     if ((int)root_log2order > lnu) return NTT_E_LENGTH;
@@ -714,6 +732,27 @@ ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t* root) {
     if ((int)log2n > lnu) return NTT_E_LENGTH;
     // 2^(nu/N): the harmonic of exact order N
     *root = powmod64(2, (1ull << lnu) >> log2n, m);
+    return NTT_OK;
+}
+
+ntt_status ntt_max_log2n(uint64_t m, uint32_t* log2n) {
+    if (!log2n) return NTT_E_ARG;
+    const int v2 = modulus_info(m).second;
+    if (v2 < 0) return NTT_E_MODULUS;
+    *log2n = (uint32_t)v2;
+    return NTT_OK;
+}
+
+ntt_status ntt_euler_root(uint64_t m, uint32_t log2n, uint64_t* root) {
+    if (!root) return NTT_E_ARG;
+    const int v2 = modulus_info(m).second;
+    if (v2 < 0) return NTT_E_MODULUS;
+    if ((int)log2n > v2) return NTT_E_LENGTH;
+    // the smallest quadratic non-residue z (z^((m-1)/2) = -1); z^((m-1)/N) then
+    // has exact order N, since its N/2-th power is z^((m-1)/2)
+    uint64_t z = 2;
+    while (powmod64(z, (m - 1) / 2, m) != m - 1) ++z;
+    *root = powmod64(z, (m - 1) >> log2n, m);
     return NTT_OK;
 }
 

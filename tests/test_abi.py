@@ -35,6 +35,10 @@ def lib():
     L.ntt_default_root.restype = I32
     L.ntt_modulus_order.argtypes = [U64, ctypes.POINTER(U32)]
     L.ntt_modulus_order.restype = I32
+    L.ntt_max_log2n.argtypes = [U64, ctypes.POINTER(U32)]
+    L.ntt_max_log2n.restype = I32
+    L.ntt_euler_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
+    L.ntt_euler_root.restype = I32
     L.ntt_status_string.argtypes = [I32]
     L.ntt_status_string.restype = ctypes.c_char_p
     return L
@@ -119,3 +123,24 @@ def test_flag_values_match_header():
     assert flags, "no flags in the header"
     for name, val in flags.items():
         assert getattr(nt, "FLAG_" + name) == int(val, 16), name
+
+
+def test_euler_form_queries_and_validation(lib):
+    import paper_1005_1497_amd as nt
+    out = ctypes.c_uint32(0)
+    for m, v2 in ((7340033, 20), (13631489, 20), (998244353, 23), (31065037602817, 19)):
+        assert lib.ntt_max_log2n(m, ctypes.byref(out)) == 0 and out.value == v2
+    assert lib.ntt_max_log2n(341, ctypes.byref(out)) == 2
+    r = ctypes.c_uint64(0)
+    for m, n in ((7340033, 20), (7340033, 7), (13631489, 20), (998244353, 22)):
+        assert lib.ntt_euler_root(m, n, ctypes.byref(r)) == 0
+        assert pow(r.value, 1 << n, m) == 1 and pow(r.value, 1 << (n - 1), m) == m - 1
+    assert lib.ntt_euler_root(7340033, 21, ctypes.byref(r)) == 3
+    c = lib.conv_circular
+    E = nt.FLAG_EULER
+    w10 = pow(3, (7340033 - 1) >> 10, 7340033)   # 3 generates Z_7340033^*
+    assert pow(w10, 512, 7340033) == 7340033 - 1
+    assert c(7340033, 10, w10, 32, BAD, BAD, ctypes.c_void_p(0x200000), 0, None) == 2   # not a Rader prime
+    assert c(7340033, 10, pow(w10, 2, 7340033), 32, BAD, BAD, ctypes.c_void_p(0x200000), E, None) == 4
+    assert c(7340033, 21, w10, 32, BAD, BAD, ctypes.c_void_p(0x200000), E, None) == 3   # 2^21 does not divide m - 1
+    assert c(341, 2, 4, 32, BAD, BAD, ctypes.c_void_p(0x200000), E, None) == 2           # composite

@@ -296,3 +296,53 @@ def test_worked_example_f17():
     exp = [(lin[j] if j < len(lin) else 0) % 17 for j in range(8)]
     assert oracle.conv_via_ntt(f, g, 17, 2).tolist() == exp
     assert oracle.conv_direct(f, g, 17).tolist() == exp
+
+
+# ---------------------------------------------------------------- Euler form
+# Sec. I, Eq. 4 (Pollard's form by Euler's theorem): primes k*2^n + 1 whose
+# roots of unity are not powers of two.  The root below is built here with
+# Python integers (the smallest quadratic non-residue z, raised to (p-1)/N), and
+# its order is checked against the definition before the oracle is trusted.
+EULER_PRIMES = [(7340033, 20), (5767169, 19), (998244353, 23), (469762049, 26)]
+
+
+def _euler_root(p, n):
+    z = 2
+    while pow(z, (p - 1) // 2, p) != p - 1:
+        z += 1
+    return pow(z, (p - 1) >> n, p)
+
+
+@pytest.mark.parametrize("p,v2", EULER_PRIMES)
+def test_euler_primes_and_root_order(p, v2):
+    assert oracle.is_prime(p)
+    assert (p - 1) % (1 << v2) == 0 and ((p - 1) >> v2) % 2 == 1
+    w = _euler_root(p, 10)
+    assert pow(w, 512, p) == p - 1 and pow(w, 1024, p) == 1
+    assert oracle.order(w, p, 4096) == 1024
+    # 2 itself is not a lambda-root of order 2^k for these primes
+    o2 = oracle.order(2, p, 1 << 22)
+    assert o2 == 0 or o2 & (o2 - 1) != 0
+
+
+@pytest.mark.parametrize("p,v2", EULER_PRIMES)
+@pytest.mark.parametrize("N", [1, 2, 8, 64])
+def test_euler_convolution_theorem_and_closed_forms(p, v2, N):
+    n = N.bit_length() - 1
+    w = _euler_root(p, n)
+    rng = np.random.default_rng(N + p % 97)
+    dtype = np.uint64
+    f = rng.integers(0, p, N, dtype=dtype)
+    g = rng.integers(0, p, N, dtype=dtype)
+    assert np.array_equal(oracle.conv_via_ntt(f, g, p, w), oracle.conv_direct(f, g, p))
+    d1 = np.zeros(N, dtype)
+    if N > 1:
+        d1[1] = 1
+        assert [int(v) for v in oracle.ntt(d1, p, w)] == [pow(w, u, p) for u in range(N)]
+    x = rng.integers(0, p, N, dtype=dtype)
+    assert np.array_equal(oracle.ntt(oracle.ntt(x, p, w), p, w, inverse=True), x)
+    # the inverse includes N^-1: checked with Python integers
+    X = oracle.ntt(x, p, w)
+    t = N // 3
+    ref = sum(int(X[u]) * pow(w, (-u * t) % N, p) for u in range(N)) * pow(N, p - 2, p) % p
+    assert int(oracle.ntt(X, p, w, inverse=True)[t]) == ref
