@@ -63,6 +63,8 @@ def _load():
             lib.oracle_conv_entries.argtypes = [_u64p, _u64p, U64, U64, _u64p, U64, _u64p]
             lib.oracle_conv_via_ntt.argtypes = [_u64p, _u64p, _u64p, U64, U64, U64]
             lib.oracle_conv_via_ntt.restype = INT
+            lib.oracle_deconv_via_ntt.argtypes = [_u64p, _u64p, _u64p, U64, U64, U64]
+            lib.oracle_deconv_via_ntt.restype = INT
             _lib = lib
     return _lib
 
@@ -149,4 +151,22 @@ def conv_via_ntt(f, g, m: int, root: int) -> np.ndarray:
     rc = _load().oracle_conv_via_ntt(_p(fa), _p(ga), _p(out), fa.size, int(m), int(root))
     if rc:
         raise ValueError("oracle_conv_via_ntt failed with code %d" % rc)
+    return out
+
+
+class Singular(ValueError):
+    """A spectral coefficient of the divisor is zero: no unique quotient."""
+
+
+def deconv_via_ntt(f, h, m: int, root: int) -> np.ndarray:
+    """Exact deconvolution (Sec. III-A, prime modulus): the g with f * g = h,
+    inverse(forward(h) / forward(f)), all O(N^2).  Raises Singular when some
+    forward(f) bin is zero."""
+    fa, ha = _arr(f), _arr(h)
+    out = np.zeros_like(fa)
+    rc = _load().oracle_deconv_via_ntt(_p(fa), _p(ha), _p(out), fa.size, int(m), int(root))
+    if rc == 4:
+        raise Singular("a spectral coefficient of f is zero")
+    if rc:
+        raise ValueError("oracle_deconv_via_ntt failed with code %d" % rc)
     return out

@@ -201,3 +201,27 @@ int oracle_conv_via_ntt(const uint64_t *f, const uint64_t *g, uint64_t *h,
     free(F); free(G);
     return rc;
 }
+
+/* Exact deconvolution (division filtering): the prime modulus lets every
+ * nonzero coefficient be divided (Sec. III-A), so f * g = h is solved for g by
+ * the convolution theorem read backwards (Sec. I):
+ *     g = inverse( forward(h) / forward(f) ),
+ * each spectral quotient H(u) F(u)^-1 with F(u)^-1 from the extended Euclidean
+ * algorithm (Appendix A).  Returns 4 (and leaves g unspecified) when some
+ * F(u) = 0, where no unique g exists; otherwise as oracle_ntt. */
+int oracle_deconv_via_ntt(const uint64_t *f, const uint64_t *h, uint64_t *g,
+                          uint64_t N, uint64_t m, uint64_t root) {
+    if (N == 0) return 0;
+    uint64_t *F = (uint64_t *)malloc((size_t)N * sizeof(uint64_t));
+    uint64_t *H = (uint64_t *)malloc((size_t)N * sizeof(uint64_t));
+    if (!F || !H) { free(F); free(H); return 3; }
+    int rc = oracle_ntt(f, F, N, m, root, 0);
+    if (!rc) rc = oracle_ntt(h, H, N, m, root, 0);
+    for (uint64_t u = 0; !rc && u < N; ++u) {
+        if (F[u] == 0) { rc = 4; break; }
+        H[u] = mulmod(H[u], oracle_inverse(F[u], m), m);
+    }
+    if (!rc) rc = oracle_ntt(H, g, N, m, root, 1);
+    free(F); free(H);
+    return rc;
+}

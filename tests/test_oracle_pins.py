@@ -20,6 +20,9 @@ normalisation, an overflow) would fail:
   conv_via_ntt     equals conv_direct (convolution theorem) for every Table 1
                    prime and every N up to min(N_Max, 1024); independent of which
                    primitive N-th root is used.
+  deconv_via_ntt   recovers g from f and conv_direct(f, g); brute force over all
+                   g for tiny N; a shift by a delta undone; the all-ones
+                   divisor (spectrum N*delta_0) reported singular.
   ntt_bins /       equal the matching entries of the full O(N^2) outputs.
   conv_entries
 """
@@ -346,3 +349,56 @@ def test_euler_convolution_theorem_and_closed_forms(p, v2, N):
     t = N // 3
     ref = sum(int(X[u]) * pow(w, (-u * t) % N, p) for u in range(N)) * pow(N, p - 2, p) % p
     assert int(oracle.ntt(X, p, w, inverse=True)[t]) == ref
+
+
+
+# ---------------------------------------------------------------- deconvolution
+# Division filtering (Sec. III-A: the prime modulus makes every nonzero
+# coefficient invertible).  Pinned by conv_direct (itself pinned above), by
+# brute force, and by closed forms.
+@pytest.mark.parametrize("m,nu", [(17, 8), (257, 16), (641, 64), (13631489, 524288)])
+@pytest.mark.parametrize("N", [1, 2, 8, 32])
+def test_deconv_recovers_g(m, nu, N):
+    if N > nu:
+        pytest.skip("N must divide nu")
+    root = pow(2, nu // N, m)
+    rng = np.random.default_rng(m % 1000 + N)
+    g = rng.integers(0, m, N, dtype=np.uint64)
+    for _ in range(50):
+        f = rng.integers(0, m, N, dtype=np.uint64)
+        try:
+            out = oracle.deconv_via_ntt(f, oracle.conv_direct(f, g, m), m, root)
+        except oracle.Singular:
+            continue
+        assert np.array_equal(out, g)
+        return
+    pytest.fail("no invertible divisor drawn")
+
+
+def test_deconv_brute_force_tiny():
+    # m = 17, N = 4, root 2^(8/4) = 4: the unique g with f * g = h among all 17^4
+    m, N, root = 17, 4, 4
+    f = [3, 1, 0, 5]
+    h = [int(v) for v in oracle.conv_direct(np.array(f, np.uint64), np.array([2, 7, 11, 0], np.uint64), m)]
+    sols = []
+    for a in range(m):
+        for b in range(m):
+            for c in range(m):
+                for d in range(m):
+                    gg = (a, b, c, d)
+                    if all(sum(f[k] * gg[(j - k) % N] for k in range(N)) % m == h[j] for j in range(N)):
+                        sols.append(gg)
+    assert sols == [(2, 7, 11, 0)]
+    out = oracle.deconv_via_ntt(np.array(f, np.uint64), np.array(h, np.uint64), m, root)
+    assert tuple(int(v) for v in out) == sols[0]
+
+
+def test_deconv_shift_and_singular():
+    m, nu, N = 13631489, 524288, 64
+    root = pow(2, nu // N, m)
+    h = np.random.default_rng(3).integers(0, m, N, dtype=np.uint64)
+    d = np.zeros(N, np.uint64)
+    d[5] = 1                                   # f = delta_5: g is h shifted back by 5
+    assert np.array_equal(oracle.deconv_via_ntt(d, h, m, root), np.roll(h, -5))
+    with pytest.raises(oracle.Singular):       # all ones: spectrum N * delta_0
+        oracle.deconv_via_ntt(np.ones(N, np.uint64), h, m, root)
