@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
-    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler"], default="batch",
                     help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
                          "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests")
@@ -120,6 +120,8 @@ def main():
         return uneven_bench(args)
     if args.workload == "single":
         return single_bench(args)
+    if args.workload in ("deconv", "euler"):
+        return variant_bench(args)
 
     import torch
     import paper_1005_1497_amd as nt
@@ -324,6 +326,65 @@ def single_bench(args):
         res[w.name] = {"p50_us": float(np.percentile(per, 50) * 1e3), "p99_us": float(np.percentile(per, 99) * 1e3),
                        "conv_per_s": 1e3 / float(per.mean())}
     print(json.dumps({"metric": "single convolution latency", "results": res}), flush=True)
+
+
+def variant_bench(args):
+    """The adjacent transforms on the headline shape, 4096 x N = 2^16:
+    deconv  exact deconvolution g = inverse(forward(h) / forward(f)),
+            m = 13631489 (rows in 1 GiB scratch chunks, four-step launches,
+            Fermat inverses), against conv_circular-style convolution of the
+            same rows through the same launches (flag FLAG_PER_CLASS form);
+    euler   the batch convolution with the Euler-form prime 7340033 = 7*2^20+1
+            and a root of order 2^16 that is not a power of two."""
+    import torch
+    import paper_1005_1497_amd as nt
+    import seeded_inputs as si
+    count, n = 4096, 16
+    N = 1 << n
+    st = torch.cuda.current_stream()
+    if args.workload == "deconv":
+        m = si.M_13631489
+        rng = np.random.default_rng(7)
+        f = torch.from_numpy(rng.integers(0, m, (count, N), dtype=np.uint32).view(np.int32)).cuda()
+        h = torch.from_numpy(rng.integers(0, m, (count, N), dtype=np.uint32).view(np.int32)).cuda()
+        g = torch.empty_like(f)
+
+        def run():
+            try:
+                nt.deconvolve(f, h, m, out=g, stream=st)
+            except nt.NttError as e:          # a singular draw still times the full path
+                if e.name != "NTT_E_SINGULAR":
+                    raise
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        out = {"metric": "exact deconvolutions/s, 4096 x N=2^16", "value": count / (ms / 1e3), "unit": "deconv/s",
+               "ms_per_step": ms, "config": {"workload": "deconv4096_n65536_m13631489", "count": count, "n": N},
+               "note": "includes the singular-coefficient readback and stream synchronisation of every call"}
+    else:
+        m = 7340033
+        root = nt.euler_root(m, 20)
+        rng = np.random.default_rng(8)
+        f = torch.from_numpy(rng.integers(0, m, count * N, dtype=np.uint32).view(np.int32)).cuda()
+        g = torch.from_numpy(rng.integers(0, m, count * N, dtype=np.uint32).view(np.int32)).cuda()
+        h = torch.empty_like(f)
+        desc = nt.BatchDesc([n] * count, si.offsets([n] * count))
+        run = lambda: nt.conv_batched(f, g, desc, m, root=root, root_log2order=20, out=h, flags=nt.FLAG_EULER,
+                                      stream=st)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        per = _time_ms(run, args.steps, st)
+        ms = float(per.mean())
+        out = {"metric": "exact convolutions/s, Euler-form prime, 4096 x N=2^16", "value": count / (ms / 1e3),
+               "unit": "conv/s", "ms_per_step": ms,
+               "config": {"workload": "euler4096_n65536_m7340033", "count": count, "n": N, "root": root}}
+    print(json.dumps(out), flush=True)
 
 
 def serve_bench(args):

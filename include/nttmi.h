@@ -47,7 +47,10 @@ typedef enum {
     NTT_E_RANGE = 5,        /* an operand >= m, only with NTT_FLAG_CHECK_RANGE */
     NTT_E_NOMEM = 6,        /* device or host allocation failed */
     NTT_E_DEVICE = 7,       /* a HIP runtime call or kernel launch failed */
-    NTT_E_UNSUPPORTED = 8   /* a valid request this build does not implement */
+    NTT_E_UNSUPPORTED = 8,  /* a valid request this build does not implement (64-bit
+                               words: m >= 2^46; lengths above 2^22) */
+    NTT_E_SINGULAR = 9      /* conv_deconvolve: a spectral coefficient of the divisor
+                               is zero, so no unique quotient exists */
 } ntt_status;
 
 /* Flags (bitwise OR). */
@@ -127,6 +130,21 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc *d, const void *f, const void *g, void *h,
                         uint32_t flags, void *stream);
+
+/* Exact deconvolution (division filtering): a prime modulus makes every
+ * nonzero coefficient invertible (Sec. III-A), so f * g = h (Eq. 1) is solved
+ * for g by the convolution theorem read backwards (Sec. I):
+ *     g = inverse( forward(h) / forward(f) ),
+ * the spectral quotients formed with Fermat inverses F(u)^(m-2).  `batch` rows
+ * of N = 2^log2n contiguous elements; row r of g solves row r of f and h.
+ * Same requirements on m, N and root as conv_circular (NTT_FLAG_EULER
+ * applies).  Returns NTT_E_SINGULAR when some forward(f) coefficient of some
+ * row is zero (g is then unspecified).  Synchronises the stream (it reads that
+ * verdict back), so it is not for use while the stream is being captured.
+ * g may equal h (in place); partial overlap is NTT_E_ARG. */
+ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
+                           const void *f, const void *h, void *g, uint32_t batch,
+                           uint32_t flags, void *stream);
 
 /* The default root for length 2^log2n: 2^(nu / N), nu = ord_m(2) (the harmonic
  * of the digital circle of Eq. 5 that has exact order N).  Writes it to *root. */

@@ -21,7 +21,7 @@ import os
 import torch
 
 __all__ = [
-    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched",
+    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve",
     "default_root", "modulus_order", "release_caches", "status_string",
     "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "STATUS",
     "euler_root", "max_log2n",
@@ -32,7 +32,7 @@ LIB_PATH = os.path.join(_HERE, "libnttmi.so")
 
 STATUS = {
     0: "NTT_OK", 1: "NTT_E_ARG", 2: "NTT_E_MODULUS", 3: "NTT_E_LENGTH", 4: "NTT_E_ROOT",
-    5: "NTT_E_RANGE", 6: "NTT_E_NOMEM", 7: "NTT_E_DEVICE", 8: "NTT_E_UNSUPPORTED",
+    5: "NTT_E_RANGE", 6: "NTT_E_NOMEM", 7: "NTT_E_DEVICE", 8: "NTT_E_UNSUPPORTED", 9: "NTT_E_SINGULAR",
 }
 FLAG_CHECK_RANGE = 0x1
 FLAG_PER_ITEM = 0x2
@@ -40,7 +40,7 @@ FLAG_PER_CLASS = 0x4
 FLAG_AUTOTUNE = 0x8
 FLAG_EULER = 0x10
 
-EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "ntt_default_root",
+EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "ntt_default_root",
            "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches")
 
 
@@ -71,6 +71,8 @@ def _load():
         fn.restype = I32
     L.conv_circular.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, VP]
     L.conv_circular.restype = I32
+    L.conv_deconvolve.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, U32, VP]
+    L.conv_deconvolve.restype = I32
     L.conv_batched.argtypes = [U64, U64, U32, U32, ctypes.POINTER(_BatchDesc), VP, VP, VP, U32, VP]
     L.conv_batched.restype = I32
     L.ntt_default_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
@@ -199,6 +201,29 @@ def conv_circular(f: torch.Tensor, g: torch.Tensor, m: int, root: int | None = N
     _check(lib.conv_circular(int(m), log2n, int(root), bits, ctypes.c_void_p(f.data_ptr()),
                              ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(flags),
                              _stream(stream)), "conv_circular")
+    return out
+
+
+def deconvolve(f: torch.Tensor, h: torch.Tensor, m: int, root: int | None = None, out=None, flags: int = 0,
+               stream=None):
+    """Exact deconvolution: the g with f * g = h (Eq. 1) along the last
+    dimension, g = inverse(forward(h) / forward(f)).  Raises NttError
+    (NTT_E_SINGULAR) when a forward(f) coefficient is zero.  Synchronises."""
+    bits = _words(f, "f")
+    if _words(h, "h") != bits or h.shape != f.shape:
+        raise ValueError("f and h must match in shape and word width")
+    N = f.shape[-1]
+    log2n = _log2(N)
+    batch = f.numel() // N if f.numel() else 0
+    if root is None:
+        root = _root(m, log2n, flags)
+    if out is None:
+        out = torch.empty_like(f)
+    elif _words(out, "out") != bits or out.shape != f.shape:
+        raise ValueError("out must match f")
+    _check(lib.conv_deconvolve(int(m), log2n, int(root), bits, ctypes.c_void_p(f.data_ptr()),
+                               ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch, int(flags),
+                               _stream(stream)), "conv_deconvolve")
     return out
 
 

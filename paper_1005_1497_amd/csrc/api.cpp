@@ -121,8 +121,10 @@ ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu, uint32_t flag
     if (*lnu < 0) return NTT_E_MODULUS;
     if (elem_bits == 32 && m >= (1ull << 24)) return NTT_E_MODULUS;
     if (elem_bits == 64 && m >= (1ull << 62)) return NTT_E_MODULUS;
-    // 64-bit words: residues are carried exactly in fp64, which holds m < 2^50
-    if (elem_bits == 64 && m >= (1ull << 50)) return NTT_E_UNSUPPORTED;
+    // 64-bit words: residues are carried exactly in fp64; the bounds of the
+    // double-product reduction close (pass outputs <= 11 m, products exact)
+    // for m < 2^46
+    if (elem_bits == 64 && m >= (1ull << 46)) return NTT_E_UNSUPPORTED;
     return NTT_OK;
 }
 
@@ -644,6 +646,58 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
     return conv_one(p, elem_bits, log2n, f, g, h, stream);
 }
 
+ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* f,
+                           const void* h, void* g, uint32_t batch, uint32_t flags, void* stream) {
+    int lnu = 0;
+    ntt_status st = validate(m, log2n, root, elem_bits, &lnu, flags);
+    if (st != NTT_OK) return st;
+    if (batch == 0) return NTT_OK;
+    if (!f || !h || !g) return NTT_E_ARG;
+    const size_t wb = elem_bits / 8;
+    const size_t bytes = ((size_t)batch << log2n) * wb;
+    if (overlap(f, bytes, g, bytes) == 2 || overlap(h, bytes, g, bytes) == 2) return NTT_E_ARG;
+    if (flags & NTT_FLAG_CHECK_RANGE) {
+        st = check_range(elem_bits, f, (uint64_t)batch << log2n, m, stream);
+        if (st == NTT_OK) st = check_range(elem_bits, h, (uint64_t)batch << log2n, m, stream);
+        if (st != NTT_OK) return st;
+    }
+    const Plan* p = nullptr;
+    st = get_plan(m, log2n, root, lnu, &p);
+    if (st != NTT_OK) return st;
+    void* flag = nullptr;
+    st = get_buf(caches().flag, stream, sizeof(uint32_t), &flag);
+    if (st != NTT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s);
+    if (e != hipSuccess) return hip_status(e);
+    const char* F = (const char*)f;
+    const char* Hh = (const char*)h;
+    char* Gg = (char*)g;
+    const uint64_t N = 1ull << log2n;
+    if ((int)log2n <= SMALL_MAX_LOG2N) {
+        e = launch_conv_small((int)elem_bits, log2n, F, Hh, Gg, nullptr, batch, p->dev, s, SMALL_TILE_256,
+                              (uint32_t*)flag);
+    } else {
+        // rows in chunks whose scratch (2N words each) stays within 1 GiB
+        const uint64_t per = ((uint64_t)2 * wb) << log2n;
+        const uint32_t chunk = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (1ull << 30) / per), 65535);
+        void* ws = nullptr;
+        st = get_buf(caches().work, stream, (size_t)(std::min<uint32_t>(chunk, batch) * per), &ws);
+        if (st != NTT_OK) return st;
+        for (uint32_t r = 0; r < batch && e == hipSuccess; r += chunk) {
+            const uint32_t k = std::min(chunk, batch - r);
+            const size_t o = (size_t)r * N * wb;
+            e = launch_conv_fourstep((int)elem_bits, log2n, F + o, Hh + o, Gg + o, k, N, ws, p->dev, s,
+                                     (uint32_t*)flag);
+        }
+    }
+    uint32_t hflag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e);
+    return hflag ? NTT_E_SINGULAR : NTT_OK;
+}
+
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc* d, const void* f, const void* g, void* h, uint32_t flags,
                         void* stream) {
@@ -775,6 +829,7 @@ const char* ntt_status_string(ntt_status s) {
         case NTT_E_NOMEM: return "out of memory";
         case NTT_E_DEVICE: return "HIP runtime or launch failure";
         case NTT_E_UNSUPPORTED: return "valid request not supported by this build";
+        case NTT_E_SINGULAR: return "a spectral coefficient of the divisor is zero (no unique quotient)";
     }
     return "unknown status";
 }

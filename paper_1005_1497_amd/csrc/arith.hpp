@@ -72,11 +72,14 @@ namespace nttmi {
 //
 // W32: 32-bit words, m < 2^24.  Twiddle products use the three-FMA form above
 //      with a precomputed w/m.  Scratch words are int32.
-// W64: 64-bit words, m < 2^50 (the 45-bit Rader prime of the serving
-//      workload).  A product b*w (up to ~2^94) is split exactly into
+// W64: 64-bit words, m < 2^46 (the 45-bit Rader prime of the serving
+//      workload).  A product b*w (up to ~2^96) is split exactly into
 //      hi = fl(b w) and lo = fma(b, w, -hi); the quotient q = round(hi/m) comes
-//      from an fp64 multiply; r = fma(-q, m, hi) + lo is exact because
-//      hi - q m is an integer below 2^53.  |r| <= 0.55 m for |b| <= 12 m.
+//      from an fp64 multiply-add, |q - b w / m| <= 1/2 + |b| 2^-52;
+//      r = fma(-q, m, hi) + lo is exact because hi - q m is an integer below
+//      2^53.  |r| <= m/2 + |b| m 2^-52 <= 0.69 m for |b| <= 12 m and m < 2^46,
+//      so a radix-16 pass output is at most 16 * 0.69 m < 12 m: the bounds
+//      close, and every value stays below 2^53.
 //      Scratch words are the fp64 values themselves.
 // ---------------------------------------------------------------------------
 struct W32 {
@@ -93,6 +96,7 @@ struct W32 {
     __device__ static __forceinline__ word canon(double y, const ModC& M) { return canon_u32(y, M); }
     __device__ static __forceinline__ sword to_s(double y) { return (int32_t)y; }
     __device__ static __forceinline__ double from_s(sword v) { return (double)v; }
+    __device__ static __forceinline__ double reduce_s(double y, const ModC& M) { return reduce(y, M); }
 };
 
 __device__ __forceinline__ double mulmod_dd(double b, double w, const ModC& M) {
@@ -134,6 +138,21 @@ struct W64 {
     }
     __device__ static __forceinline__ sword to_s(double y) { return y; }
     __device__ static __forceinline__ double from_s(sword v) { return v; }
+    __device__ static __forceinline__ double reduce_s(double y, const ModC& M) { return reduce_dd(y, M); }
 };
+
+// x^e mod m by left-to-right square and multiply over the bits of e (bit
+// `top` is the highest set bit; e and top are uniform across the wave, so the
+// branch is too).  x reduced; result reduced.  With e = m - 2 this is the
+// inverse of x for a prime m (Fermat's little theorem), 0 for x = 0.
+template <class W>
+__device__ __forceinline__ double pow_mod(double x, uint64_t e, int top, const ModC& M) {
+    double r = x;
+    for (int b = top - 1; b >= 0; --b) {
+        r = W::mul_var(r, r, M);
+        if ((e >> b) & 1) r = W::mul_var(r, x, M);
+    }
+    return r;
+}
 
 }  // namespace nttmi

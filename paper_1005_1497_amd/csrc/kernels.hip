@@ -37,15 +37,39 @@ constexpr int small_s(int L) { return L < 16 ? 256 : 4096 / L; }
 constexpr int small_s_wave(int L) { return L < 16 ? 64 : (L <= 1024 ? 1024 / L : 1); }
 constexpr int small_threads(int L, int S) { return L < 16 ? S : S * (L / 16); }
 
+// Pointwise step between the forward and inverse transforms.  OP_MUL, the
+// convolution (Eq. 1 by the convolution theorem, Sec. I): F * (G N^-1).
+// OP_DIV, the deconvolution (division filtering; the prime modulus makes every
+// nonzero coefficient invertible, Sec. III-A): (G N^-1) / F, with F reduced and
+// inverted as F^(m-2) (Fermat); a zero F sets *singular (the quotient is then
+// meaningless, and the caller reports it).  F and G are forward outputs
+// (|.| <= 8m + 32 for 32-bit words, < 12 m for 64-bit words).
+enum { OP_MUL = 0, OP_DIV = 1 };
+template <class W, int OP>
+__device__ __forceinline__ double spectral(double F, double G, const DevPlan& p, const ModC& M,
+                                           uint32_t* singular) {
+    const double gs = W::mul_tw(G, make_double2(p.ninv, p.ninvq), M);
+    if constexpr (OP == OP_MUL) {
+        return W::mul_var(F, gs, M);
+    } else {
+        const double fr = W::reduce_s(F, M);
+        if (fr == 0.0) atomicOr(singular, 1u);
+        const uint64_t e = (uint64_t)M.m - 2;
+        const int top = 63 - __builtin_clzll(e);
+        return W::mul_var(pow_mod<W>(fr, e, top, M), gs, M);
+    }
+}
+
 // One tile of S convolutions of length L <= 2^12, entirely in the LDS of one
 // workgroup of S * max(1, L/16) threads: forward(f), forward(g), the product
 // with N^-1 folded in, inverse and the canonical store.  Item s of the tile
 // starts at offs[s] (offs != null) or at base + s L; items s >= cnt are
 // computed on item 0's data and not stored.
-template <class W, int L, int S>
+template <class W, int L, int S, int OP = OP_MUL>
 __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const typename W::word* g,
                                                 typename W::word* h, const uint64_t* offs, uint64_t base,
-                                                uint32_t cnt, const DevPlan& p, double* lds, int tid) {
+                                                uint32_t cnt, const DevPlan& p, double* lds, int tid,
+                                                uint32_t* singular = nullptr) {
     using B = Blk<L, S, POS_FAST>;
     int s, j;
     B::item(tid, s, j);
@@ -66,12 +90,9 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(g[off + B::pos0(j, i)], M);
     block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
-    // pointwise product with N^-1 folded in: F * (G * N^-1)
+    // pointwise step with N^-1 folded in
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) {
-        const double gs = W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M);
-        v[i] = W::mul_var(W::from_s(F[i]), gs, M);
-    }
+    for (int i = 0; i < B::E; ++i) v[i] = spectral<W, OP>(W::from_s(F[i]), v[i], p, M, singular);
     if (B::R0 != B::RL) {
         // output positions of the forward transform differ from the input
         // positions of the inverse: reorder through LDS
@@ -89,14 +110,15 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
     }
 }
 
-template <class W, int L, int S>
+template <class W, int L, int S, int OP>
 __global__ __launch_bounds__(256) void k_conv_small(const typename W::word* f, const typename W::word* g,
                                                     typename W::word* h, const uint64_t* __restrict__ offs,
-                                                    uint32_t count, DevPlan p) {
+                                                    uint32_t count, DevPlan p, uint32_t* singular) {
     __shared__ double lds[Blk<L, S, POS_FAST>::LDS_DOUBLES];
     const uint64_t first = (uint64_t)blockIdx.x * S;
     const uint32_t cnt = (uint32_t)(count - first < (uint64_t)S ? count - first : (uint64_t)S);
-    small_conv_tile<W, L, S>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds, threadIdx.x);
+    small_conv_tile<W, L, S, OP>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds, threadIdx.x,
+                                 singular);
 }
 
 template <class W, int L, bool INV>
@@ -419,9 +441,10 @@ __device__ __forceinline__ RowIn<W, LOGN> row_conv_load(const typename W::sword*
     return in;
 }
 
-template <class W, int LOGN>
+template <class W, int LOGN, int OP = OP_MUL>
 __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typename W::sword* Yf, int r0,
-                                                 const DevPlan& p, const FSLds<LOGN>& L) {
+                                                 const DevPlan& p, const FSLds<LOGN>& L,
+                                                 uint32_t* singular = nullptr) {
     using G = FS<LOGN>;
     using B = typename G::BR;
     int s, j;
@@ -442,10 +465,7 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
                                                   twtab<W, G::A>(L.rowf, M));
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) {
-        const double gs = W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M);
-        v[i] = W::mul_var(F[i], gs, M);
-    }
+    for (int i = 0; i < B::E; ++i) v[i] = spectral<W, OP>(F[i], v[i], p, M, singular);
     if (B::R0 != B::RL) {
 #pragma unroll
         for (int i = 0; i < B::E; ++i) L.xch[B::lds(s, B::posL(j, i))] = v[i];
@@ -463,10 +483,11 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i));
 }
 
-template <class W, int LOGN>
+template <class W, int LOGN, int OP = OP_MUL>
 __device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const typename W::sword* Yg, int r0,
-                                               const DevPlan& p, const FSLds<LOGN>& L) {
-    row_conv_compute<W, LOGN>(row_conv_load<W, LOGN>(Yf, Yg, r0), Yf, r0, p, L);
+                                               const DevPlan& p, const FSLds<LOGN>& L,
+                                               uint32_t* singular = nullptr) {
+    row_conv_compute<W, LOGN, OP>(row_conv_load<W, LOGN>(Yf, Yg, r0), Yf, r0, p, L, singular);
 }
 
 // Column phase, inverse: length-B inverse transforms of scratch columns,
@@ -569,12 +590,13 @@ __global__ __launch_bounds__(512) void k_fs_col_fwd(const typename W::word* x, t
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     col_fwd_block<W, LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
 }
-template <class W, int LOGN>
+template <class W, int LOGN, int OP>
 __global__ __launch_bounds__(512) void k_fs_row_conv(typename W::sword* Yf, const typename W::sword* Yg,
-                                                     uint64_t ystride, DevPlan p) {
+                                                     uint64_t ystride, DevPlan p, uint32_t* singular) {
     __shared__ double lds[FSLds<LOGN>::WORDS];
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
-    row_conv_block<W, LOGN>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p, L);
+    row_conv_block<W, LOGN, OP>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR,
+                                p, L, singular);
 }
 template <class W, int LOGN, bool SCALE>
 __global__ __launch_bounds__(512) void k_fs_col_inv(const typename W::sword* Y, typename W::word* x,
@@ -827,22 +849,24 @@ hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, 
 
 // ------------------------------------------------------------------ launchers
 
-template <class W, int L, int S>
+template <class W, int L, int S, int OP = OP_MUL>
 static hipError_t conv_small_launch(const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
-                                    const DevPlan& p, hipStream_t st) {
+                                    const DevPlan& p, hipStream_t st, uint32_t* singular = nullptr) {
     using T = typename W::word;
-    hipLaunchKernelGGL((k_conv_small<W, L, S>), dim3((count + S - 1) / S), dim3(small_threads(L, S)), 0, st,
-                       (const T*)f, (const T*)g, (T*)h, offs, count, p);
+    hipLaunchKernelGGL((k_conv_small<W, L, S, OP>), dim3((count + S - 1) / S), dim3(small_threads(L, S)), 0, st,
+                       (const T*)f, (const T*)g, (T*)h, offs, count, p, singular);
     return hipGetLastError();
 }
 
 template <class W>
 static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
-                               const DevPlan& p, hipStream_t st, int tile) {
+                               const DevPlan& p, hipStream_t st, int tile, uint32_t* singular) {
     switch (logn) {
 #define CASE(n)                                                                                                   \
     case n:                                                                                                       \
-        return tile == SMALL_TILE_WAVE                                                                            \
+        return singular ? conv_small_launch<W, 1 << n, small_s(1 << n), OP_DIV>(f, g, h, offs, count, p, st,     \
+                                                                                 singular)                        \
+               : tile == SMALL_TILE_WAVE                                                                          \
                    ? conv_small_launch<W, 1 << n, small_s_wave(1 << n)>(f, g, h, offs, count, p, st)            \
                    : conv_small_launch<W, 1 << n, small_s(1 << n)>(f, g, h, offs, count, p, st);
         NTT_SMALL_CASES(CASE)
@@ -853,10 +877,10 @@ static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, 
 }
 
 hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, const DevPlan& p, hipStream_t st, int tile) {
+                             uint32_t count, const DevPlan& p, hipStream_t st, int tile, uint32_t* singular) {
     if (count == 0) return hipSuccess;
-    return wbits == 32 ? conv_small_t<W32>(logn, f, g, h, offs, count, p, st, tile)
-                       : conv_small_t<W64>(logn, f, g, h, offs, count, p, st, tile);
+    return wbits == 32 ? conv_small_t<W32>(logn, f, g, h, offs, count, p, st, tile, singular)
+                       : conv_small_t<W64>(logn, f, g, h, offs, count, p, st, tile, singular);
 }
 
 template <class W>
@@ -891,7 +915,8 @@ hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* 
 
 template <class W>
 static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* h, uint32_t items,
-                                  uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st) {
+                                  uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
+                                  uint32_t* singular) {
     using T = typename W::word;
     using SW = typename W::sword;
     switch (logn) {
@@ -905,8 +930,12 @@ static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* 
                            item_stride, ys, p);                                                                   \
         hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)g, Yg,     \
                            item_stride, ys, p);                                                                   \
-        hipLaunchKernelGGL((k_fs_row_conv<W, n>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf, (const SW*)Yg, \
-                           ys, p);                                                                                \
+        if (singular)                                                                                             \
+            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_DIV>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
+                               (const SW*)Yg, ys, p, singular);                                                   \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_MUL>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
+                               (const SW*)Yg, ys, p, singular);                                                   \
         hipLaunchKernelGGL((k_fs_col_inv<W, n, false>), dim3(G::A / G::SC, items), dim3(G::T), 0, st,              \
                            (const SW*)Yf, (T*)h, item_stride, ys, p);                                             \
         return hipGetLastError();                                                                                 \
@@ -919,10 +948,11 @@ static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* 
 }
 
 hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
-                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st) {
+                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
+                                uint32_t* singular) {
     if (items == 0) return hipSuccess;
-    return wbits == 32 ? conv_fourstep_t<W32>(logn, f, g, h, items, item_stride, scratch, p, st)
-                       : conv_fourstep_t<W64>(logn, f, g, h, items, item_stride, scratch, p, st);
+    return wbits == 32 ? conv_fourstep_t<W32>(logn, f, g, h, items, item_stride, scratch, p, st, singular)
+                       : conv_fourstep_t<W64>(logn, f, g, h, items, item_stride, scratch, p, st, singular);
 }
 
 template <class W>

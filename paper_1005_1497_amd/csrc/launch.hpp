@@ -22,17 +22,21 @@ struct DevPlan {
 constexpr int SMALL_MAX_LOG2N = 12;
 constexpr int MAX_LOG2N = 22;   // no prime below 2^24 has nu = 2^23; 64-bit words use the same kernels
 
-// wbits = 32 (uint32 words, m < 2^24) or 64 (uint64 words, m < 2^50).
+// wbits = 32 (uint32 words, m < 2^24) or 64 (uint64 words, m < 2^46).
 // tile: SMALL_TILE_256 (4096/N convolutions per 256-thread workgroup) or
 // SMALL_TILE_WAVE (one wave per workgroup up to N = 1024).
 enum { SMALL_TILE_256 = 0, SMALL_TILE_WAVE = 1 };
+// singular != null: deconvolution, h = inverse(forward(g) / forward(f)); a zero
+// forward(f) coefficient sets *singular (convolution otherwise).
 hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, const DevPlan& p, hipStream_t st, int tile = SMALL_TILE_256);
+                             uint32_t count, const DevPlan& p, hipStream_t st, int tile = SMALL_TILE_256,
+                             uint32_t* singular = nullptr);
 hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
                             hipStream_t st);
 // scratch: items * 2N scratch words (conv), batch * N (ntt); scratch words are wbits/8 bytes
 hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
-                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st);
+                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
+                                uint32_t* singular = nullptr);
 hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
                                const DevPlan& p, hipStream_t st);
 // scratch: grid * 2N scratch words; queue: two uint32 work-queue words, zero

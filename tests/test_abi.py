@@ -28,6 +28,8 @@ def lib():
     U64, U32, I32, VP = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
     L.conv_circular.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, VP]
     L.conv_circular.restype = I32
+    L.conv_deconvolve.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, U32, VP]
+    L.conv_deconvolve.restype = I32
     for n in ("ntt_forward", "ntt_inverse"):
         getattr(L, n).argtypes = [U64, U32, U64, U32, VP, VP, U32, U32, VP]
         getattr(L, n).restype = I32
@@ -56,7 +58,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for s in range(9):
+    for s in range(10):
         assert lib.ntt_status_string(s)
     assert b"unknown" in lib.ntt_status_string(99)
 
@@ -144,3 +146,15 @@ def test_euler_form_queries_and_validation(lib):
     assert c(7340033, 10, pow(w10, 2, 7340033), 32, BAD, BAD, ctypes.c_void_p(0x200000), E, None) == 4
     assert c(7340033, 21, w10, 32, BAD, BAD, ctypes.c_void_p(0x200000), E, None) == 3   # 2^21 does not divide m - 1
     assert c(341, 2, 4, 32, BAD, BAD, ctypes.c_void_p(0x200000), E, None) == 2           # composite
+
+
+
+def test_deconvolve_validation(lib):
+    d = lib.conv_deconvolve
+    G = ctypes.c_void_p(0x200000)
+    assert d(341, 2, 4, 32, BAD, BAD, G, 1, 0, None) == 2                       # composite modulus
+    assert d(M, 20, 2, 32, BAD, BAD, G, 1, 0, None) == 3                        # N does not divide nu
+    assert d(M, 10, 2, 32, BAD, BAD, G, 1, 0, None) == 4                        # root of the wrong order
+    assert d(M, 10, pow(2, 512, M), 32, BAD, BAD, G, 0, 0, None) == 0           # empty batch
+    assert d(M, 10, pow(2, 512, M), 32, None, BAD, G, 1, 0, None) == 1          # null
+    assert d(M, 10, pow(2, 512, M), 32, BAD, BAD, ctypes.c_void_p(0x100000 + 64), 1, 0, None) == 1  # overlap
