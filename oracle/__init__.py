@@ -65,6 +65,8 @@ def _load():
             lib.oracle_conv_via_ntt.restype = INT
             lib.oracle_deconv_via_ntt.argtypes = [_u64p, _u64p, _u64p, U64, U64, U64]
             lib.oracle_deconv_via_ntt.restype = INT
+            lib.oracle_conv_integer.argtypes = [_u64p, _u64p, _u64p, U64]
+            lib.oracle_conv_integer.restype = INT
             _lib = lib
     return _lib
 
@@ -169,4 +171,17 @@ def deconv_via_ntt(f, h, m: int, root: int) -> np.ndarray:
         raise Singular("a spectral coefficient of f is zero")
     if rc:
         raise ValueError("oracle_deconv_via_ntt failed with code %d" % rc)
+    return out
+
+
+def conv_integer(f, g) -> np.ndarray:
+    """The true integer circular convolution (Eq. 1 without the modulus), as
+    the O(N^2) direct sum; uint64 results (ValueError if one reaches 2^64)."""
+    fa, ga = _arr(f), _arr(g)
+    if fa.size != ga.size:
+        raise ValueError("f and g must have the same length")
+    out = np.zeros_like(fa)
+    rc = _load().oracle_conv_integer(_p(fa), _p(ga), _p(out), fa.size)
+    if rc:
+        raise ValueError("oracle_conv_integer: a result does not fit 64 bits")
     return out

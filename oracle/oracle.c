@@ -225,3 +225,27 @@ int oracle_deconv_via_ntt(const uint64_t *f, const uint64_t *h, uint64_t *g,
     free(F); free(H);
     return rc;
 }
+
+/* The true integer circular convolution, Eq. 1 without the reduction modulo m:
+ *     h(j) = sum_{k<N} f(k) g(j - k mod N),
+ * f and g read as non-negative integers.  This is what the convolution modulo
+ * m equals when every h(j) < m (Sec. I: "impervious to overflow" only inside
+ * the modulus), and what a residue-number (CRT) combination of convolutions
+ * modulo several primes reconstructs.  Returns 5 if some h(j) >= 2^64. */
+int oracle_conv_integer(const uint64_t *f, const uint64_t *g, uint64_t *h, uint64_t N) {
+    long long n = (long long)N;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (long long j = 0; j < n; ++j) {
+        u128 acc = 0;
+        for (uint64_t k = 0; k < N; ++k) {
+            uint64_t idx = ((uint64_t)j + N - k) % N;
+            u128 p = (u128)f[k] * g[idx];
+            if (acc + p < acc) bad = 1;
+            acc += p;
+        }
+        if (acc >> 64) bad = 1;
+        h[j] = (uint64_t)acc;
+    }
+    return bad ? 5 : 0;
+}

@@ -23,6 +23,8 @@ normalisation, an overflow) would fail:
   deconv_via_ntt   recovers g from f and conv_direct(f, g); brute force over all
                    g for tiny N; a shift by a delta undone; the all-ones
                    divisor (spectrum N*delta_0) reported singular.
+  conv_integer     numpy integer circular convolution (np.convolve folded mod N)
+                   and Python big integers; overflow past 2^64 reported.
   ntt_bins /       equal the matching entries of the full O(N^2) outputs.
   conv_entries
 """
@@ -402,3 +404,27 @@ def test_deconv_shift_and_singular():
     assert np.array_equal(oracle.deconv_via_ntt(d, h, m, root), np.roll(h, -5))
     with pytest.raises(oracle.Singular):       # all ones: spectrum N * delta_0
         oracle.deconv_via_ntt(np.ones(N, np.uint64), h, m, root)
+
+
+
+# ---------------------------------------------------------------- exact integers
+@pytest.mark.parametrize("N,bits", [(1, 31), (8, 20), (64, 15), (256, 12)])
+def test_conv_integer_vs_numpy(N, bits):
+    rng = np.random.default_rng(N + bits)
+    f = rng.integers(0, 1 << bits, N, dtype=np.uint64)
+    g = rng.integers(0, 1 << bits, N, dtype=np.uint64)
+    lin = np.convolve(f.astype(object), g.astype(object))
+    ref = [0] * N
+    for i, v in enumerate(lin):
+        ref[i % N] += int(v)
+    assert [int(v) for v in oracle.conv_integer(f, g)] == ref
+
+
+def test_conv_integer_big_and_overflow():
+    N = 16
+    f = np.full(N, (1 << 32) - 1, np.uint64)
+    g = np.full(N, (1 << 27) - 1, np.uint64)
+    ref = N * ((1 << 32) - 1) * ((1 << 27) - 1)          # below 2^64
+    assert all(int(v) == ref for v in oracle.conv_integer(f, g))
+    with pytest.raises(ValueError):
+        oracle.conv_integer(np.full(N, 1 << 62, np.uint64), np.full(N, 4, np.uint64))
