@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
-    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt"], default="batch",
                     help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
                          "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests")
@@ -120,7 +120,7 @@ def main():
         return uneven_bench(args)
     if args.workload == "single":
         return single_bench(args)
-    if args.workload in ("deconv", "euler"):
+    if args.workload in ("deconv", "euler", "crt"):
         return variant_bench(args)
 
     import torch
@@ -366,6 +366,20 @@ def variant_bench(args):
         out = {"metric": "exact deconvolutions/s, 4096 x N=2^16", "value": count / (ms / 1e3), "unit": "deconv/s",
                "ms_per_step": ms, "config": {"workload": "deconv4096_n65536_m13631489", "count": count, "n": N},
                "note": "includes the singular-coefficient readback and stream synchronisation of every call"}
+    elif args.workload == "crt":
+        rng = np.random.default_rng(9)
+        f = torch.from_numpy(rng.integers(0, 1 << 15, (count, N), dtype=np.uint32).view(np.int32)).cuda()
+        g = torch.from_numpy(rng.integers(0, 1 << 15, (count, N), dtype=np.uint32).view(np.int32)).cuda()
+        h = torch.empty((count, N), dtype=torch.int64, device="cuda")
+        run = lambda: nt.conv_crt(f, g, out=h, stream=st)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        per = _time_ms(run, args.steps, st)
+        ms = float(per.mean())
+        out = {"metric": "exact integer convolutions/s (two primes + CRT), 4096 x N=2^16, 15-bit operands",
+               "value": count / (ms / 1e3), "unit": "conv/s", "ms_per_step": ms,
+               "config": {"workload": "crt4096_n65536_15bit", "count": count, "n": N, "primes": [13631489, 7340033]}}
     else:
         m = 7340033
         root = nt.euler_root(m, 20)

@@ -146,6 +146,19 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
                            const void *f, const void *h, void *g, uint32_t batch,
                            uint32_t flags, void *stream);
 
+/* Exact integer circular convolution (Eq. 1 without the modulus) by residue
+ * number arithmetic: the convolution modulo the Rader prime 13631489 =
+ * 13 * 2^20 + 1 and modulo the Euler-form prime 7340033 = 7 * 2^20 + 1,
+ * combined by the Chinese remainder theorem into the unique value in
+ * [0, 13631489 * 7340033) (about 1.0006e14, 2^46.5).  f and g: `batch` rows of
+ * N = 2^log2n uint32 words, read as non-negative integers; h: uint64 words.
+ * h equals the true integer convolution whenever every true value is below
+ * that product (e.g. N <= 2^16 with operands below 2^15); otherwise it is the
+ * true value modulo the product.  log2n <= 19.  h may not overlap f or g.
+ * Asynchronous; capturable after a first call on the stream. */
+ntt_status conv_crt(uint32_t log2n, const void *f, const void *g, void *h, uint32_t batch,
+                    uint32_t flags, void *stream);
+
 /* The default root for length 2^log2n: 2^(nu / N), nu = ord_m(2) (the harmonic
  * of the digital circle of Eq. 5 that has exact order N).  Writes it to *root. */
 ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t *root);

@@ -67,6 +67,8 @@ def _load():
             lib.oracle_deconv_via_ntt.restype = INT
             lib.oracle_conv_integer.argtypes = [_u64p, _u64p, _u64p, U64]
             lib.oracle_conv_integer.restype = INT
+            lib.oracle_conv_integer_entries.argtypes = [_u64p, _u64p, U64, _u64p, U64, _u64p]
+            lib.oracle_conv_integer_entries.restype = INT
             _lib = lib
     return _lib
 
@@ -184,4 +186,15 @@ def conv_integer(f, g) -> np.ndarray:
     rc = _load().oracle_conv_integer(_p(fa), _p(ga), _p(out), fa.size)
     if rc:
         raise ValueError("oracle_conv_integer: a result does not fit 64 bits")
+    return out
+
+
+def conv_integer_entries(f, g, idx) -> np.ndarray:
+    """Selected outputs of conv_integer, each the O(N) direct sum."""
+    fa, ga = _arr(f), _arr(g)
+    ia = _arr(idx)
+    out = np.zeros(ia.size, dtype=np.uint64)
+    rc = _load().oracle_conv_integer_entries(_p(fa), _p(ga), fa.size, _p(ia), ia.size, _p(out))
+    if rc:
+        raise ValueError("oracle_conv_integer_entries: a result does not fit 64 bits")
     return out

@@ -249,3 +249,20 @@ int oracle_conv_integer(const uint64_t *f, const uint64_t *g, uint64_t *h, uint6
     }
     return bad ? 5 : 0;
 }
+
+/* Selected outputs of the integer circular convolution: out[i] = h(idx[i]),
+ * each the O(N) direct sum.  Returns 5 if one reaches 2^64. */
+int oracle_conv_integer_entries(const uint64_t *f, const uint64_t *g, uint64_t N,
+                                const uint64_t *idx, uint64_t nidx, uint64_t *out) {
+    long long ni = (long long)nidx;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (long long i = 0; i < ni; ++i) {
+        uint64_t j = idx[i] % N;
+        u128 acc = 0;
+        for (uint64_t k = 0; k < N; ++k) acc += (u128)f[k] * g[(j + N - k) % N];
+        if (acc >> 64) bad = 1;
+        out[i] = (uint64_t)acc;
+    }
+    return bad ? 5 : 0;
+}

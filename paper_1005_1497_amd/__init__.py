@@ -21,7 +21,7 @@ import os
 import torch
 
 __all__ = [
-    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve",
+    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt",
     "default_root", "modulus_order", "release_caches", "status_string",
     "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "STATUS",
     "euler_root", "max_log2n",
@@ -40,7 +40,8 @@ FLAG_PER_CLASS = 0x4
 FLAG_AUTOTUNE = 0x8
 FLAG_EULER = 0x10
 
-EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "ntt_default_root",
+EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "conv_crt",
+           "ntt_default_root",
            "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches")
 
 
@@ -73,6 +74,8 @@ def _load():
     L.conv_circular.restype = I32
     L.conv_deconvolve.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, U32, VP]
     L.conv_deconvolve.restype = I32
+    L.conv_crt.argtypes = [U32, VP, VP, VP, U32, U32, VP]
+    L.conv_crt.restype = I32
     L.conv_batched.argtypes = [U64, U64, U32, U32, ctypes.POINTER(_BatchDesc), VP, VP, VP, U32, VP]
     L.conv_batched.restype = I32
     L.ntt_default_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
@@ -224,6 +227,25 @@ def deconvolve(f: torch.Tensor, h: torch.Tensor, m: int, root: int | None = None
     _check(lib.conv_deconvolve(int(m), log2n, int(root), bits, ctypes.c_void_p(f.data_ptr()),
                                ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch, int(flags),
                                _stream(stream)), "conv_deconvolve")
+    return out
+
+
+def conv_crt(f: torch.Tensor, g: torch.Tensor, out=None, stream=None):
+    """Exact integer circular convolution along the last dimension (uint32
+    operands, int64/uint64 result) from convolutions modulo 13631489 and
+    7340033 combined by the Chinese remainder theorem; exact while every true
+    value is below their product (about 1.0006e14)."""
+    if _words(f, "f") != 32 or _words(g, "g") != 32 or g.shape != f.shape:
+        raise ValueError("f and g must be 32-bit words of the same shape")
+    N = f.shape[-1]
+    log2n = _log2(N)
+    batch = f.numel() // N if f.numel() else 0
+    if out is None:
+        out = torch.empty(f.shape, dtype=torch.int64, device=f.device)
+    elif _words(out, "out") != 64 or out.shape != f.shape:
+        raise ValueError("out must be 64-bit words of f's shape")
+    _check(lib.conv_crt(log2n, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                        ctypes.c_void_p(out.data_ptr()), batch, 0, _stream(stream)), "conv_crt")
     return out
 
 

@@ -698,6 +698,46 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
     return hflag ? NTT_E_SINGULAR : NTT_OK;
 }
 
+ntt_status conv_crt(uint32_t log2n, const void* f, const void* g, void* h, uint32_t batch, uint32_t flags,
+                    void* stream) {
+    (void)flags;
+    // the Rader prime 13 2^20 + 1 (root 2^(nu/N)) and the Euler-form prime
+    // 7 2^20 + 1 (root z^((m2-1)/N), z = 3 the smallest non-residue)
+    const uint64_t m1 = 13631489, m2 = 7340033;
+    if (log2n > 19) return NTT_E_LENGTH;
+    if (batch == 0) return NTT_OK;
+    if (!f || !g || !h) return NTT_E_ARG;
+    const uint64_t N = 1ull << log2n;
+    const size_t in_bytes = (size_t)batch * N * 4, out_bytes = (size_t)batch * N * 8;
+    if (overlap(f, in_bytes, h, out_bytes) || overlap(g, in_bytes, h, out_bytes)) return NTT_E_ARG;
+    int l1 = 0, l2 = 0;
+    ntt_status st = check_modulus(m1, 32, &l1);
+    if (st == NTT_OK) st = check_modulus(m2, 32, &l2, NTT_FLAG_EULER);
+    if (st != NTT_OK) return st;
+    uint64_t r1 = 0, r2 = 0;
+    st = ntt_default_root(m1, log2n, &r1);
+    if (st == NTT_OK) st = ntt_euler_root(m2, log2n, &r2);
+    if (st != NTT_OK) return st;
+    const Plan *p1 = nullptr, *p2 = nullptr;
+    st = get_plan(m1, log2n, r1, l1, &p1);
+    if (st == NTT_OK) st = get_plan(m2, log2n, r2, l2, &p2);
+    if (st != NTT_OK) return st;
+    // residues of both convolutions, then their combination
+    void* tmp = nullptr;
+    st = get_buf(caches().tune, stream, 2 * in_bytes, &tmp);
+    if (st != NTT_OK) return st;
+    uint32_t* a1 = (uint32_t*)tmp;
+    uint32_t* a2 = a1 + (size_t)batch * N;
+    std::vector<uint64_t> off(batch);
+    for (uint32_t i = 0; i < batch; ++i) off[i] = (uint64_t)i * N;
+    hipStream_t s = (hipStream_t)stream;
+    st = launch_class(log2n, off, p1, 32, (const char*)f, (const char*)g, (char*)a1, s, stream);
+    if (st == NTT_OK) st = launch_class(log2n, off, p2, 32, (const char*)f, (const char*)g, (char*)a2, s, stream);
+    if (st != NTT_OK) return st;
+    const uint32_t c = (uint32_t)powmod64(m1 % m2, m2 - 2, m2);   // m1^-1 mod m2
+    return hip_status(launch_crt_combine(a1, a2, (uint64_t*)h, (uint64_t)batch * N, (uint32_t)m1, (uint32_t)m2, c, s));
+}
+
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc* d, const void* f, const void* g, void* h, uint32_t flags,
                         void* stream) {

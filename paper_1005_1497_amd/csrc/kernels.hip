@@ -823,6 +823,38 @@ __global__ __launch_bounds__(512, 2) void k_conv_multi(const typename W::word* f
     queue_leave(queue);
 }
 
+// ------------------------------------------------------------------ residue combination
+// Chinese remainder combination of two convolutions modulo the primes m1, m2:
+// h = a1 + m1 t, t = ((a2 - a1) m1^-1) mod m2, the unique integer in
+// [0, m1 m2) congruent to a1 mod m1 and to a2 mod m2 (exact, in fp64 residues:
+// every product is below 2^47).  c = m1^-1 mod m2; M2 the constants of m2.
+__global__ void k_crt_combine(const uint32_t* __restrict__ a1, const uint32_t* __restrict__ a2,
+                              uint64_t* __restrict__ h, uint64_t n, uint32_t m1, double c, ModC M2) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double x1 = (double)a1[i];
+        const double d = reduce((double)a2[i] - x1, M2);              // a2 - a1 mod m2, |d| <= m2/2 + 2
+        double t = mulmod_var(d, c, M2);                              // in [-m2/2 - 2, m2/2 + 2]
+        t = (t < 0.0) ? t + M2.m : t;
+        t = (t >= M2.m) ? t - M2.m : t;
+        h[i] = (uint64_t)x1 + (uint64_t)m1 * (uint64_t)t;
+    }
+}
+
+hipError_t launch_crt_combine(const uint32_t* a1, const uint32_t* a2, uint64_t* h, uint64_t n, uint32_t m1,
+                              uint32_t m2, uint32_t c, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    ModC M2;
+    M2.m = (double)m2;
+    M2.minv = 1.0 / (double)m2;
+    M2.C = 6755399441055744.0;
+    M2.Cm = M2.C * (double)m2;
+    M2.c32 = (double)((1ull << 32) % m2);
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_crt_combine, dim3((uint32_t)blocks), dim3(256), 0, st, a1, a2, h, n, m1, (double)c, M2);
+    return hipGetLastError();
+}
+
 // Sets *flag when some x[i] >= m.
 template <class T>
 __global__ void k_range_check(const T* __restrict__ x, uint64_t n, T m, uint32_t* flag) {

@@ -58,6 +58,10 @@ int multi_max_log2n(int wbits);
 int multi_tile(int logn);            // convolutions per task below 2^(SMALL_MAX_LOG2N + 1)
 int multi_blocks_per_cu(int wbits);
 int fused_threads(int logn);
+// h[i] = the integer in [0, m1 m2) that is a1[i] mod m1 and a2[i] mod m2 (m1, m2
+// primes below 2^24, a1 < m1, a2 < m2); c = m1^-1 mod m2.
+hipError_t launch_crt_combine(const uint32_t* a1, const uint32_t* a2, uint64_t* h, uint64_t n, uint32_t m1,
+                              uint32_t m2, uint32_t c, hipStream_t st);
 hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st);
 
 }  // namespace nttmi

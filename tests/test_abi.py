@@ -30,6 +30,8 @@ def lib():
     L.conv_circular.restype = I32
     L.conv_deconvolve.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, U32, VP]
     L.conv_deconvolve.restype = I32
+    L.conv_crt.argtypes = [U32, VP, VP, VP, U32, U32, VP]
+    L.conv_crt.restype = I32
     for n in ("ntt_forward", "ntt_inverse"):
         getattr(L, n).argtypes = [U64, U32, U64, U32, VP, VP, U32, U32, VP]
         getattr(L, n).restype = I32
@@ -158,3 +160,13 @@ def test_deconvolve_validation(lib):
     assert d(M, 10, pow(2, 512, M), 32, BAD, BAD, G, 0, 0, None) == 0           # empty batch
     assert d(M, 10, pow(2, 512, M), 32, None, BAD, G, 1, 0, None) == 1          # null
     assert d(M, 10, pow(2, 512, M), 32, BAD, BAD, ctypes.c_void_p(0x100000 + 64), 1, 0, None) == 1  # overlap
+
+
+
+def test_crt_validation(lib):
+    c = lib.conv_crt
+    H = ctypes.c_void_p(0x4000000)
+    assert c(20, BAD, BAD, H, 1, 0, None) == 3                                  # beyond 2^19
+    assert c(10, BAD, BAD, H, 0, 0, None) == 0                                  # empty batch
+    assert c(10, None, BAD, H, 1, 0, None) == 1                                 # null
+    assert c(10, BAD, BAD, ctypes.c_void_p(0x100000 + 1024), 1, 0, None) == 1   # h overlaps f

@@ -428,3 +428,13 @@ def test_conv_integer_big_and_overflow():
     assert all(int(v) == ref for v in oracle.conv_integer(f, g))
     with pytest.raises(ValueError):
         oracle.conv_integer(np.full(N, 1 << 62, np.uint64), np.full(N, 4, np.uint64))
+
+
+
+def test_conv_integer_entries_match_full():
+    rng = np.random.default_rng(77)
+    N = 512
+    f = rng.integers(0, 1 << 20, N, dtype=np.uint64)
+    g = rng.integers(0, 1 << 20, N, dtype=np.uint64)
+    idx = np.array([0, 1, 200, 511], np.uint64)
+    assert np.array_equal(oracle.conv_integer_entries(f, g, idx), oracle.conv_integer(f, g)[idx.astype(int)])
