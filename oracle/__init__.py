@@ -69,6 +69,8 @@ def _load():
             lib.oracle_conv_integer.restype = INT
             lib.oracle_conv_integer_entries.argtypes = [_u64p, _u64p, U64, _u64p, U64, _u64p]
             lib.oracle_conv_integer_entries.restype = INT
+            lib.oracle_conv2d_direct.argtypes = [_u64p, _u64p, _u64p, U64, U64, U64]
+            lib.oracle_conv2d_entries.argtypes = [_u64p, _u64p, U64, U64, U64, _u64p, U64, _u64p]
             _lib = lib
     return _lib
 
@@ -197,4 +199,27 @@ def conv_integer_entries(f, g, idx) -> np.ndarray:
     rc = _load().oracle_conv_integer_entries(_p(fa), _p(ga), fa.size, _p(ia), ia.size, _p(out))
     if rc:
         raise ValueError("oracle_conv_integer_entries: a result does not fit 64 bits")
+    return out
+
+
+def conv2d_direct(f, g, m: int) -> np.ndarray:
+    """Two-dimensional circular convolution of R x C arrays, the O(R^2 C^2)
+    direct sum modulo m; returns an R x C uint64 array."""
+    fa, ga = np.asarray(f), np.asarray(g)
+    if fa.shape != ga.shape or fa.ndim != 2:
+        raise ValueError("f and g must be equal 2-D arrays")
+    R, C = fa.shape
+    out = np.zeros(R * C, dtype=np.uint64)
+    _load().oracle_conv2d_direct(_p(_arr(fa.ravel())), _p(_arr(ga.ravel())), _p(out), R, C, int(m))
+    return out.reshape(R, C)
+
+
+def conv2d_entries(f, g, m: int, idx) -> np.ndarray:
+    """Selected outputs (flat row-major indices) of conv2d_direct."""
+    fa, ga = np.asarray(f), np.asarray(g)
+    R, C = fa.shape
+    ia = _arr(idx)
+    out = np.zeros(ia.size, dtype=np.uint64)
+    _load().oracle_conv2d_entries(_p(_arr(fa.ravel())), _p(_arr(ga.ravel())), R, C, int(m), _p(ia), ia.size,
+                                  _p(out))
     return out

@@ -266,3 +266,39 @@ int oracle_conv_integer_entries(const uint64_t *f, const uint64_t *g, uint64_t N
     }
     return bad ? 5 : 0;
 }
+
+/* Two-dimensional circular convolution of R x C arrays (row-major), the
+ * multi-dimensional form of Eq. 1 (Sec. I mentions multi-dimensional
+ * techniques; the transform applies to each dimension in turn):
+ *     h(i, j) = < sum_{k<R} sum_{l<C} f(k, l) g((i - k) mod R, (j - l) mod C) >_m,
+ * as the O(R^2 C^2) direct sum. */
+void oracle_conv2d_direct(const uint64_t *f, const uint64_t *g, uint64_t *h,
+                          uint64_t R, uint64_t C, uint64_t m) {
+    long long n = (long long)(R * C);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long long o = 0; o < n; ++o) {
+        uint64_t i = (uint64_t)o / C, j = (uint64_t)o % C;
+        u128 acc = 0;
+        for (uint64_t k = 0; k < R; ++k)
+            for (uint64_t l = 0; l < C; ++l) {
+                uint64_t a = (i + R - k) % R, b = (j + C - l) % C;
+                acc += (u128)mulmod(f[k * C + l], g[a * C + b], m);
+            }
+        h[o] = (uint64_t)(acc % m);
+    }
+}
+
+/* Selected outputs of the 2-D convolution: out[q] = h(idx[q] / C, idx[q] % C). */
+void oracle_conv2d_entries(const uint64_t *f, const uint64_t *g, uint64_t R, uint64_t C,
+                           uint64_t m, const uint64_t *idx, uint64_t nidx, uint64_t *out) {
+    long long ni = (long long)nidx;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long long q = 0; q < ni; ++q) {
+        uint64_t o = idx[q] % (R * C), i = o / C, j = o % C;
+        u128 acc = 0;
+        for (uint64_t k = 0; k < R; ++k)
+            for (uint64_t l = 0; l < C; ++l)
+                acc += (u128)mulmod(f[k * C + l], g[((i + R - k) % R) * C + (j + C - l) % C], m);
+        out[q] = (uint64_t)(acc % m);
+    }
+}

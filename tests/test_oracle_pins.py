@@ -25,6 +25,9 @@ normalisation, an overflow) would fail:
                    divisor (spectrum N*delta_0) reported singular.
   conv_integer     numpy integer circular convolution (np.convolve folded mod N)
                    and Python big integers; overflow past 2^64 reported.
+  conv2d_direct    numpy 2-D circular convolution by shifted sums; a 1 x C
+                   array reduces to conv_direct; separable operands give the
+                   outer product of the 1-D convolutions.
   ntt_bins /       equal the matching entries of the full O(N^2) outputs.
   conv_entries
 """
@@ -438,3 +441,35 @@ def test_conv_integer_entries_match_full():
     g = rng.integers(0, 1 << 20, N, dtype=np.uint64)
     idx = np.array([0, 1, 200, 511], np.uint64)
     assert np.array_equal(oracle.conv_integer_entries(f, g, idx), oracle.conv_integer(f, g)[idx.astype(int)])
+
+
+
+# ---------------------------------------------------------------- 2-D convolution
+def test_conv2d_vs_numpy_rolls():
+    m = 13631489
+    rng = np.random.default_rng(12)
+    R, C = 4, 8
+    f = rng.integers(0, 50, (R, C), dtype=np.uint64)
+    g = rng.integers(0, 50, (R, C), dtype=np.uint64)
+    ref = np.zeros((R, C), dtype=np.int64)
+    for k in range(R):
+        for l in range(C):
+            ref += int(f[k, l]) * np.roll(np.roll(g.astype(np.int64), k, axis=0), l, axis=1)
+    assert np.array_equal(oracle.conv2d_direct(f, g, m), (ref % m).astype(np.uint64))
+
+
+def test_conv2d_reduces_to_1d_and_separates():
+    m = 13631489
+    rng = np.random.default_rng(13)
+    a = rng.integers(0, m, 16, dtype=np.uint64)
+    b = rng.integers(0, m, 16, dtype=np.uint64)
+    assert np.array_equal(oracle.conv2d_direct(a[None, :], b[None, :], m)[0], oracle.conv_direct(a, b, m))
+    assert np.array_equal(oracle.conv2d_direct(a[:, None], b[:, None], m)[:, 0], oracle.conv_direct(a, b, m))
+    # separable: (p x q) conv (r x s) = conv(p, r) x conv(q, s), products mod m
+    p, q = rng.integers(0, m, 8, dtype=np.uint64), rng.integers(0, m, 4, dtype=np.uint64)
+    r, s = rng.integers(0, m, 8, dtype=np.uint64), rng.integers(0, m, 4, dtype=np.uint64)
+    outer = lambda x, y: np.array([[int(u) * int(v) % m for v in y] for u in x], dtype=np.uint64)
+    lhs = oracle.conv2d_direct(outer(p, q), outer(r, s), m)
+    assert np.array_equal(lhs, outer(oracle.conv_direct(p, r, m), oracle.conv_direct(q, s, m)))
+    idx = np.array([0, 5, 31], np.uint64)
+    assert np.array_equal(oracle.conv2d_entries(outer(p, q), outer(r, s), m, idx), lhs.ravel()[idx.astype(int)])
