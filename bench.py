@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
-    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt", "conv2d"], default="batch",
                     help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
                          "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests")
@@ -120,7 +120,7 @@ def main():
         return uneven_bench(args)
     if args.workload == "single":
         return single_bench(args)
-    if args.workload in ("deconv", "euler", "crt"):
+    if args.workload in ("deconv", "euler", "crt", "conv2d"):
         return variant_bench(args)
 
     import torch
@@ -366,6 +366,21 @@ def variant_bench(args):
         out = {"metric": "exact deconvolutions/s, 4096 x N=2^16", "value": count / (ms / 1e3), "unit": "deconv/s",
                "ms_per_step": ms, "config": {"workload": "deconv4096_n65536_m13631489", "count": count, "n": N},
                "note": "includes the singular-coefficient readback and stream synchronisation of every call"}
+    elif args.workload == "conv2d":
+        m, R, C = si.M_13631489, 4096, 4096
+        rng = np.random.default_rng(10)
+        f = torch.from_numpy(rng.integers(0, m, (R, C), dtype=np.uint32).view(np.int32)).cuda()
+        g = torch.from_numpy(rng.integers(0, m, (R, C), dtype=np.uint32).view(np.int32)).cuda()
+        h = torch.empty_like(f)
+        run = lambda: nt.conv2d(f, g, m, out=h, stream=st)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        per = _time_ms(run, args.steps, st)
+        ms = float(per.mean())
+        out = {"metric": "2-D circular convolutions/s, 4096 x 4096, m = 13631489", "value": 1e3 / ms,
+               "unit": "conv2d/s", "ms_per_step": ms, "elements_per_s": R * C / (ms / 1e3),
+               "config": {"workload": "conv2d_4096x4096_m13631489", "rows": R, "cols": C}}
     elif args.workload == "crt":
         rng = np.random.default_rng(9)
         f = torch.from_numpy(rng.integers(0, 1 << 15, (count, N), dtype=np.uint32).view(np.int32)).cuda()

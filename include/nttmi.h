@@ -159,6 +159,19 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
 ntt_status conv_crt(uint32_t log2n, const void *f, const void *g, void *h, uint32_t batch,
                     uint32_t flags, void *stream);
 
+/* Two-dimensional circular convolution of R x C arrays (row-major, R = 2^log2r
+ * rows, C = 2^log2c columns), the multi-dimensional form of Eq. 1:
+ *   h(i, j) = < sum_{k, l} f(k, l) g((i - k) mod R, (j - l) mod C) >_m,
+ * computed with row transforms, a transpose and column transforms (each
+ * dimension by Eq. 2 with its own root of exact order R or C), the pointwise
+ * product, and the inverses (Eq. 3, with R^-1 and C^-1).  Same requirements on
+ * m and the roots as conv_circular, per dimension (NTT_FLAG_EULER applies);
+ * R C <= 2^31.  h may equal f or g; partial overlap is NTT_E_ARG.
+ * Asynchronous. */
+ntt_status conv2d_circular(uint64_t m, uint32_t log2r, uint32_t log2c, uint64_t root_r, uint64_t root_c,
+                           uint32_t elem_bits, const void *f, const void *g, void *h, uint32_t flags,
+                           void *stream);
+
 /* The default root for length 2^log2n: 2^(nu / N), nu = ord_m(2) (the harmonic
  * of the digital circle of Eq. 5 that has exact order N).  Writes it to *root. */
 ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t *root);

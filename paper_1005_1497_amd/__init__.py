@@ -21,7 +21,7 @@ import os
 import torch
 
 __all__ = [
-    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt",
+    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt", "conv2d",
     "default_root", "modulus_order", "release_caches", "status_string",
     "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "STATUS",
     "euler_root", "max_log2n",
@@ -41,6 +41,7 @@ FLAG_AUTOTUNE = 0x8
 FLAG_EULER = 0x10
 
 EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "conv_crt",
+           "conv2d_circular",
            "ntt_default_root",
            "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches")
 
@@ -76,6 +77,8 @@ def _load():
     L.conv_deconvolve.restype = I32
     L.conv_crt.argtypes = [U32, VP, VP, VP, U32, U32, VP]
     L.conv_crt.restype = I32
+    L.conv2d_circular.argtypes = [U64, U32, U32, U64, U64, U32, VP, VP, VP, U32, VP]
+    L.conv2d_circular.restype = I32
     L.conv_batched.argtypes = [U64, U64, U32, U32, ctypes.POINTER(_BatchDesc), VP, VP, VP, U32, VP]
     L.conv_batched.restype = I32
     L.ntt_default_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
@@ -246,6 +249,28 @@ def conv_crt(f: torch.Tensor, g: torch.Tensor, out=None, stream=None):
         raise ValueError("out must be 64-bit words of f's shape")
     _check(lib.conv_crt(log2n, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
                         ctypes.c_void_p(out.data_ptr()), batch, 0, _stream(stream)), "conv_crt")
+    return out
+
+
+def conv2d(f: torch.Tensor, g: torch.Tensor, m: int, root_r: int | None = None, root_c: int | None = None,
+           out=None, flags: int = 0, stream=None):
+    """Two-dimensional circular convolution of R x C arrays (powers of two)
+    modulo m, each dimension transformed with its own root of exact order."""
+    bits = _words(f, "f")
+    if _words(g, "g") != bits or g.shape != f.shape or f.dim() != 2:
+        raise ValueError("f and g must be 2-D with the same shape and word width")
+    log2r, log2c = _log2(f.shape[0]), _log2(f.shape[1])
+    if root_r is None:
+        root_r = _root(m, log2r, flags)
+    if root_c is None:
+        root_c = _root(m, log2c, flags)
+    if out is None:
+        out = torch.empty_like(f)
+    elif _words(out, "out") != bits or out.shape != f.shape:
+        raise ValueError("out must match f")
+    _check(lib.conv2d_circular(int(m), log2r, log2c, int(root_r), int(root_c), bits, ctypes.c_void_p(f.data_ptr()),
+                               ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(flags),
+                               _stream(stream)), "conv2d_circular")
     return out
 
 

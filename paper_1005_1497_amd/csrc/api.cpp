@@ -354,6 +354,28 @@ ntt_status conv_one(const Plan* p, uint32_t wbits, uint32_t log2n, const void* f
     return hip_status(launch_conv_fourstep((int)wbits, log2n, f, g, h, 1, 0, ws, p->dev, s));
 }
 
+// `batch` contiguous rows of N = 2^log2n, forward or inverse, plan built.  The
+// four-step path runs in chunks of rows whose scratch stays within 1 GiB.
+ntt_status ntt_rows(const Plan* p, uint32_t elem_bits, uint32_t log2n, bool inv, const void* x, void* X,
+                    uint32_t batch, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if ((int)log2n <= SMALL_MAX_LOG2N)
+        return hip_status(launch_ntt_small((int)elem_bits, log2n, inv, x, X, batch, p->dev, s));
+    const size_t wb = elem_bits / 8;
+    const uint64_t per = (uint64_t)wb << log2n;
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (1ull << 30) / per), 65535);
+    void* ws = nullptr;
+    ntt_status st = get_buf(caches().work, stream, (size_t)(std::min(chunk, batch) * per), &ws);
+    if (st != NTT_OK) return st;
+    for (uint32_t r = 0; r < batch; r += chunk) {
+        const uint32_t k = std::min(chunk, batch - r);
+        const hipError_t e = launch_ntt_fourstep((int)elem_bits, log2n, inv, (const char*)x + (size_t)r * per,
+                                                 (char*)X + (size_t)r * per, k, ws, p->dev, s);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return NTT_OK;
+}
+
 ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* x, void* X,
                    uint32_t batch, uint32_t flags, void* stream) {
     int lnu = 0;
@@ -370,13 +392,7 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
     const Plan* p = nullptr;
     st = get_plan(m, log2n, root, lnu, &p);
     if (st != NTT_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    if ((int)log2n <= SMALL_MAX_LOG2N)
-        return hip_status(launch_ntt_small((int)elem_bits, log2n, inv, x, X, batch, p->dev, s));
-    void* ws = nullptr;
-    st = get_buf(caches().work, stream, ((size_t)batch * (elem_bits / 8)) << log2n, &ws);
-    if (st != NTT_OK) return st;
-    return hip_status(launch_ntt_fourstep((int)elem_bits, log2n, inv, x, X, batch, ws, p->dev, s));
+    return ntt_rows(p, elem_bits, log2n, inv, x, X, batch, stream);
 }
 
 // One launch for the items of one length class: the LDS kernel below 2^13,
@@ -736,6 +752,53 @@ ntt_status conv_crt(uint32_t log2n, const void* f, const void* g, void* h, uint3
     if (st != NTT_OK) return st;
     const uint32_t c = (uint32_t)powmod64(m1 % m2, m2 - 2, m2);   // m1^-1 mod m2
     return hip_status(launch_crt_combine(a1, a2, (uint64_t*)h, (uint64_t)batch * N, (uint32_t)m1, (uint32_t)m2, c, s));
+}
+
+ntt_status conv2d_circular(uint64_t m, uint32_t log2r, uint32_t log2c, uint64_t root_r, uint64_t root_c,
+                           uint32_t elem_bits, const void* f, const void* g, void* h, uint32_t flags,
+                           void* stream) {
+    int lnu = 0;
+    ntt_status st = validate(m, log2r, root_r, elem_bits, &lnu, flags);
+    if (st == NTT_OK) st = validate(m, log2c, root_c, elem_bits, &lnu, flags);
+    if (st != NTT_OK) return st;
+    if (log2r + log2c > 31) return NTT_E_UNSUPPORTED;
+    if (!f || !g || !h) return NTT_E_ARG;
+    const uint32_t R = 1u << log2r, C = 1u << log2c;
+    const size_t wb = elem_bits / 8;
+    const uint64_t n = (uint64_t)R * C;
+    const size_t bytes = (size_t)n * wb;
+    if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
+    if (flags & NTT_FLAG_CHECK_RANGE) {
+        st = check_range(elem_bits, f, n, m, stream);
+        if (st == NTT_OK) st = check_range(elem_bits, g, n, m, stream);
+        if (st != NTT_OK) return st;
+    }
+    const Plan *pr = nullptr, *pc = nullptr;
+    st = get_plan(m, log2r, root_r, lnu, &pr);
+    if (st == NTT_OK) st = get_plan(m, log2c, root_c, lnu, &pc);
+    if (st != NTT_OK) return st;
+    void* ws = nullptr;
+    st = get_buf(caches().tune, stream, 2 * bytes, &ws);
+    if (st != NTT_OK) return st;
+    char* A = (char*)ws;
+    char* B = A + bytes;
+    char* H = (char*)h;
+    hipStream_t s = (hipStream_t)stream;
+    const int w = (int)elem_bits;
+    // forward: rows of f (length C), transpose, rows again (length R); the same
+    // for g (h serves as its buffer once f and g have been read); product;
+    // inverse along R (with R^-1), transpose back, inverse along C (with C^-1)
+    st = ntt_rows(pc, elem_bits, log2c, false, f, A, R, stream);
+    if (st == NTT_OK) st = hip_status(launch_transpose(w, A, B, R, C, s));
+    if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, false, B, B, C, stream);
+    if (st == NTT_OK) st = ntt_rows(pc, elem_bits, log2c, false, g, A, R, stream);
+    if (st == NTT_OK) st = hip_status(launch_transpose(w, A, H, R, C, s));
+    if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, false, H, H, C, stream);
+    if (st == NTT_OK) st = hip_status(launch_pointwise_mul(w, B, H, B, n, pr->dev.M, s));
+    if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, true, B, B, C, stream);
+    if (st == NTT_OK) st = hip_status(launch_transpose(w, B, A, C, R, s));
+    if (st == NTT_OK) st = ntt_rows(pc, elem_bits, log2c, true, A, H, R, stream);
+    return st;
 }
 
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,

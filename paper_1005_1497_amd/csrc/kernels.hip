@@ -855,6 +855,63 @@ hipError_t launch_crt_combine(const uint32_t* a1, const uint32_t* a2, uint64_t* 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ 2-D helpers
+// out (cols x rows) = transpose of in (rows x cols), row-major, through a
+// padded 32 x 32 LDS tile (coalesced reads and writes); any sizes.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* __restrict__ out, uint32_t rows,
+                                                   uint32_t cols) {
+    __shared__ T tile[32][33];
+    const uint32_t c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+    for (uint32_t k = ty; k < 32; k += 8) {
+        const uint32_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) tile[k][tx] = in[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (uint32_t k = ty; k < 32; k += 8) {
+        const uint32_t c = c0 + k, r = r0 + tx;
+        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];
+    }
+}
+
+// c = a b mod m, canonical, for canonical a, b (transform outputs).
+template <class W>
+__global__ __launch_bounds__(256) void k_pointwise_mul(const typename W::word* __restrict__ a,
+                                                       const typename W::word* __restrict__ b,
+                                                       typename W::word* __restrict__ c, uint64_t n, ModC M) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double x = W::load_reduce(a[i], M), y = W::load_reduce(b[i], M);
+        c[i] = W::canon(W::mul_var(x, y, M), M);
+    }
+}
+
+hipError_t launch_transpose(int wbits, const void* in, void* out, uint32_t rows, uint32_t cols, hipStream_t st) {
+    if (rows == 0 || cols == 0) return hipSuccess;
+    const dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+    if (wbits == 32)
+        hipLaunchKernelGGL(k_transpose<uint32_t>, grid, dim3(256), 0, st, (const uint32_t*)in, (uint32_t*)out, rows,
+                           cols);
+    else
+        hipLaunchKernelGGL(k_transpose<uint64_t>, grid, dim3(256), 0, st, (const uint64_t*)in, (uint64_t*)out, rows,
+                           cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_pointwise_mul(int wbits, const void* a, const void* b, void* c, uint64_t n, const ModC& M,
+                                hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (wbits == 32)
+        hipLaunchKernelGGL(k_pointwise_mul<W32>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint32_t*)a,
+                           (const uint32_t*)b, (uint32_t*)c, n, M);
+    else
+        hipLaunchKernelGGL(k_pointwise_mul<W64>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint64_t*)a,
+                           (const uint64_t*)b, (uint64_t*)c, n, M);
+    return hipGetLastError();
+}
+
 // Sets *flag when some x[i] >= m.
 template <class T>
 __global__ void k_range_check(const T* __restrict__ x, uint64_t n, T m, uint32_t* flag) {

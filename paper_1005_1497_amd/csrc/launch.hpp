@@ -62,6 +62,11 @@ int fused_threads(int logn);
 // primes below 2^24, a1 < m1, a2 < m2); c = m1^-1 mod m2.
 hipError_t launch_crt_combine(const uint32_t* a1, const uint32_t* a2, uint64_t* h, uint64_t n, uint32_t m1,
                               uint32_t m2, uint32_t c, hipStream_t st);
+// out (cols x rows) = transpose of in (rows x cols); words of wbits.
+hipError_t launch_transpose(int wbits, const void* in, void* out, uint32_t rows, uint32_t cols, hipStream_t st);
+// c = a b mod m for n canonical words.
+hipError_t launch_pointwise_mul(int wbits, const void* a, const void* b, void* c, uint64_t n, const ModC& M,
+                                hipStream_t st);
 hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st);
 
 }  // namespace nttmi

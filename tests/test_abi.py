@@ -32,6 +32,8 @@ def lib():
     L.conv_deconvolve.restype = I32
     L.conv_crt.argtypes = [U32, VP, VP, VP, U32, U32, VP]
     L.conv_crt.restype = I32
+    L.conv2d_circular.argtypes = [U64, U32, U32, U64, U64, U32, VP, VP, VP, U32, VP]
+    L.conv2d_circular.restype = I32
     for n in ("ntt_forward", "ntt_inverse"):
         getattr(L, n).argtypes = [U64, U32, U64, U32, VP, VP, U32, U32, VP]
         getattr(L, n).restype = I32
@@ -170,3 +172,15 @@ def test_crt_validation(lib):
     assert c(10, BAD, BAD, H, 0, 0, None) == 0                                  # empty batch
     assert c(10, None, BAD, H, 1, 0, None) == 1                                 # null
     assert c(10, BAD, BAD, ctypes.c_void_p(0x100000 + 1024), 1, 0, None) == 1   # h overlaps f
+
+
+
+def test_conv2d_validation(lib):
+    c = lib.conv2d_circular
+    H = ctypes.c_void_p(0x4000000)
+    r10, r4 = pow(2, 512, M), pow(2, 1 << 15, M)
+    assert c(M, 20, 4, 2, r4, 32, BAD, BAD, H, 0, None) == 3                  # rows beyond nu
+    assert c(M, 10, 4, r4, r4, 32, BAD, BAD, H, 0, None) == 4                 # row root of the wrong order
+    assert c(M, 10, 4, r10, r10, 32, BAD, BAD, H, 0, None) == 4               # column root of the wrong order
+    assert c(M, 10, 4, r10, r4, 32, None, BAD, H, 0, None) == 1               # null
+    assert c(M, 10, 4, r10, r4, 32, BAD, BAD, ctypes.c_void_p(0x100000 + 64), 0, None) == 1   # overlap
