@@ -42,9 +42,11 @@ def kernel_source_sha() -> str:
     while the kernels are unchanged since the counters were taken."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "blockdft.hpp", "arith.hpp", "launch.hpp"):
-        with open(os.path.join(ROOT, "paper_1005_1497_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1005_1497_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

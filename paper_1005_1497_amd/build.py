@@ -19,20 +19,28 @@ HIP_FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, f) for f in ("kernels.hip", "api.cpp")]
+    names = sorted(f for f in os.listdir(CSRC) if f.startswith("launch_") and f.endswith(".hip"))
+    return [os.path.join(CSRC, f) for f in names] + [os.path.join(CSRC, "api.cpp")]
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libnttmi.so (always recompiles)."""
-    objs = []
+    """Compile every source (in parallel) and link libnttmi.so (always recompiles)."""
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    jobs = []
     for src in sources():
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
         cmd = [HIPCC] + HIP_FLAGS + ["-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        jobs.append((subprocess.Popen(cmd), cmd, obj))
+    objs = []
+    failed = []
+    for proc, cmd, obj in jobs:
+        if proc.wait() != 0:
+            failed.append(" ".join(cmd))
         objs.append(obj)
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -1,4 +1,5 @@
-// Device kernels and their launchers (gfx950).
+// Device code of the library (gfx950): the kernels as templates, shared by
+// the launcher translation units (launch_*.hip).
 //
 // Small lengths (N <= 2^SMALL_MAX_LOG2N): one workgroup transforms whole
 // sequences in LDS; the fused convolution kernel runs forward(f), forward(g),
@@ -11,6 +12,7 @@
 // the frequency-domain order is internal, so no transpose is needed: the row
 // phase runs forward(f), forward(g), product, inverse and the inverse twiddle
 // on each row, and the last phase runs the inverse column transforms.
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -20,10 +22,6 @@
 #include "launch.hpp"
 
 namespace nttmi {
-
-// Residency target: four waves per SIMD (<= 128 VGPRs per lane) keeps two or
-// more workgroups per CU for latency hiding across barriers.
-#define NTT_OCC __attribute__((amdgpu_waves_per_eu(4, 8)))
 
 // Length cases of the launchers: log2 N handled in LDS, and by the four-step path.
 #define NTT_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
@@ -821,372 +819,6 @@ __global__ __launch_bounds__(512, 2) void k_conv_multi(const typename W::word* f
     const uint32_t t = __builtin_amdgcn_readfirstlane(queue_take(queue, &ticket));
     multi_from<W, MultiCfg<W>::NMAX>(t, f, g, h, tasks, ntasks, toffs, Y, queue, plans, lds, &ticket);
     queue_leave(queue);
-}
-
-// ------------------------------------------------------------------ residue combination
-// Chinese remainder combination of two convolutions modulo the primes m1, m2:
-// h = a1 + m1 t, t = ((a2 - a1) m1^-1) mod m2, the unique integer in
-// [0, m1 m2) congruent to a1 mod m1 and to a2 mod m2 (exact, in fp64 residues:
-// every product is below 2^47).  c = m1^-1 mod m2; M2 the constants of m2.
-__global__ void k_crt_combine(const uint32_t* __restrict__ a1, const uint32_t* __restrict__ a2,
-                              uint64_t* __restrict__ h, uint64_t n, uint32_t m1, double c, ModC M2) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const double x1 = (double)a1[i];
-        const double d = reduce((double)a2[i] - x1, M2);              // a2 - a1 mod m2, |d| <= m2/2 + 2
-        double t = mulmod_var(d, c, M2);                              // in [-m2/2 - 2, m2/2 + 2]
-        t = (t < 0.0) ? t + M2.m : t;
-        t = (t >= M2.m) ? t - M2.m : t;
-        h[i] = (uint64_t)x1 + (uint64_t)m1 * (uint64_t)t;
-    }
-}
-
-hipError_t launch_crt_combine(const uint32_t* a1, const uint32_t* a2, uint64_t* h, uint64_t n, uint32_t m1,
-                              uint32_t m2, uint32_t c, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    ModC M2;
-    M2.m = (double)m2;
-    M2.minv = 1.0 / (double)m2;
-    M2.C = 6755399441055744.0;
-    M2.Cm = M2.C * (double)m2;
-    M2.c32 = (double)((1ull << 32) % m2);
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_crt_combine, dim3((uint32_t)blocks), dim3(256), 0, st, a1, a2, h, n, m1, (double)c, M2);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ 2-D helpers
-// out (cols x rows) = transpose of in (rows x cols), row-major, through a
-// padded 32 x 32 LDS tile (coalesced reads and writes); any sizes.
-template <class T>
-__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* __restrict__ out, uint32_t rows,
-                                                   uint32_t cols) {
-    __shared__ T tile[32][33];
-    const uint32_t c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-    const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
-    for (uint32_t k = ty; k < 32; k += 8) {
-        const uint32_t r = r0 + k, c = c0 + tx;
-        if (r < rows && c < cols) tile[k][tx] = in[(size_t)r * cols + c];
-    }
-    __syncthreads();
-    for (uint32_t k = ty; k < 32; k += 8) {
-        const uint32_t c = c0 + k, r = r0 + tx;
-        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];
-    }
-}
-
-// c = a b mod m, canonical, for canonical a, b (transform outputs).
-template <class W>
-__global__ __launch_bounds__(256) void k_pointwise_mul(const typename W::word* __restrict__ a,
-                                                       const typename W::word* __restrict__ b,
-                                                       typename W::word* __restrict__ c, uint64_t n, ModC M) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const double x = W::load_reduce(a[i], M), y = W::load_reduce(b[i], M);
-        c[i] = W::canon(W::mul_var(x, y, M), M);
-    }
-}
-
-hipError_t launch_transpose(int wbits, const void* in, void* out, uint32_t rows, uint32_t cols, hipStream_t st) {
-    if (rows == 0 || cols == 0) return hipSuccess;
-    const dim3 grid((cols + 31) / 32, (rows + 31) / 32);
-    if (wbits == 32)
-        hipLaunchKernelGGL(k_transpose<uint32_t>, grid, dim3(256), 0, st, (const uint32_t*)in, (uint32_t*)out, rows,
-                           cols);
-    else
-        hipLaunchKernelGGL(k_transpose<uint64_t>, grid, dim3(256), 0, st, (const uint64_t*)in, (uint64_t*)out, rows,
-                           cols);
-    return hipGetLastError();
-}
-
-hipError_t launch_pointwise_mul(int wbits, const void* a, const void* b, void* c, uint64_t n, const ModC& M,
-                                hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (wbits == 32)
-        hipLaunchKernelGGL(k_pointwise_mul<W32>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint32_t*)a,
-                           (const uint32_t*)b, (uint32_t*)c, n, M);
-    else
-        hipLaunchKernelGGL(k_pointwise_mul<W64>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint64_t*)a,
-                           (const uint64_t*)b, (uint64_t*)c, n, M);
-    return hipGetLastError();
-}
-
-// Sets *flag when some x[i] >= m.
-template <class T>
-__global__ void k_range_check(const T* __restrict__ x, uint64_t n, T m, uint32_t* flag) {
-    uint32_t bad = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        bad |= (x[i] >= m) ? 1u : 0u;
-    if (bad) atomicOr(flag, 1u);
-}
-
-hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st) {
-    hipError_t e = hipMemsetAsync(flag, 0, sizeof(uint32_t), st);
-    if (e != hipSuccess) return e;
-    if (n == 0) return hipSuccess;
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (wbits == 32)
-        hipLaunchKernelGGL(k_range_check<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint32_t*)x, n,
-                           (uint32_t)m, flag);
-    else
-        hipLaunchKernelGGL(k_range_check<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint64_t*)x, n,
-                           (uint64_t)m, flag);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ launchers
-
-template <class W, int L, int S, int OP = OP_MUL>
-static hipError_t conv_small_launch(const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
-                                    const DevPlan& p, hipStream_t st, uint32_t* singular = nullptr) {
-    using T = typename W::word;
-    hipLaunchKernelGGL((k_conv_small<W, L, S, OP>), dim3((count + S - 1) / S), dim3(small_threads(L, S)), 0, st,
-                       (const T*)f, (const T*)g, (T*)h, offs, count, p, singular);
-    return hipGetLastError();
-}
-
-template <class W>
-static hipError_t conv_small_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs, uint32_t count,
-                               const DevPlan& p, hipStream_t st, int tile, uint32_t* singular) {
-    switch (logn) {
-#define CASE(n)                                                                                                   \
-    case n:                                                                                                       \
-        return singular ? conv_small_launch<W, 1 << n, small_s(1 << n), OP_DIV>(f, g, h, offs, count, p, st,     \
-                                                                                 singular)                        \
-               : tile == SMALL_TILE_WAVE                                                                          \
-                   ? conv_small_launch<W, 1 << n, small_s_wave(1 << n)>(f, g, h, offs, count, p, st)            \
-                   : conv_small_launch<W, 1 << n, small_s(1 << n)>(f, g, h, offs, count, p, st);
-        NTT_SMALL_CASES(CASE)
-#undef CASE
-        default:
-            return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, const DevPlan& p, hipStream_t st, int tile, uint32_t* singular) {
-    if (count == 0) return hipSuccess;
-    return wbits == 32 ? conv_small_t<W32>(logn, f, g, h, offs, count, p, st, tile, singular)
-                       : conv_small_t<W64>(logn, f, g, h, offs, count, p, st, tile, singular);
-}
-
-template <class W>
-static hipError_t ntt_small_t(int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
-                              hipStream_t st) {
-    using T = typename W::word;
-    switch (logn) {
-#define CASE(n)                                                                                                   \
-    case n: {                                                                                                     \
-        const uint32_t S = small_s(1 << n);                                                                       \
-        if (inv)                                                                                                  \
-            hipLaunchKernelGGL((k_ntt_small<W, 1 << n, true>), dim3((batch + S - 1) / S), dim3(256), 0, st,       \
-                               (const T*)x, (T*)X, batch, p);                                                     \
-        else                                                                                                      \
-            hipLaunchKernelGGL((k_ntt_small<W, 1 << n, false>), dim3((batch + S - 1) / S), dim3(256), 0, st,      \
-                               (const T*)x, (T*)X, batch, p);                                                     \
-        return hipGetLastError();                                                                                 \
-    }
-        NTT_SMALL_CASES(CASE)
-#undef CASE
-        default:
-            return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
-                            hipStream_t st) {
-    if (batch == 0) return hipSuccess;
-    return wbits == 32 ? ntt_small_t<W32>(logn, inv, x, X, batch, p, st)
-                       : ntt_small_t<W64>(logn, inv, x, X, batch, p, st);
-}
-
-template <class W>
-static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* h, uint32_t items,
-                                  uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
-                                  uint32_t* singular) {
-    using T = typename W::word;
-    using SW = typename W::sword;
-    switch (logn) {
-#define CASE(n)                                                                                                   \
-    case n: {                                                                                                     \
-        using G = FS<n>;                                                                                          \
-        const uint64_t ys = 2ull * G::N;                                                                          \
-        SW* Yf = (SW*)scratch;                                                                                    \
-        SW* Yg = Yf + G::N;                                                                                       \
-        hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)f, Yf,     \
-                           item_stride, ys, p);                                                                   \
-        hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)g, Yg,     \
-                           item_stride, ys, p);                                                                   \
-        if (singular)                                                                                             \
-            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_DIV>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
-                               (const SW*)Yg, ys, p, singular);                                                   \
-        else                                                                                                      \
-            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_MUL>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
-                               (const SW*)Yg, ys, p, singular);                                                   \
-        hipLaunchKernelGGL((k_fs_col_inv<W, n, false>), dim3(G::A / G::SC, items), dim3(G::T), 0, st,              \
-                           (const SW*)Yf, (T*)h, item_stride, ys, p);                                             \
-        return hipGetLastError();                                                                                 \
-    }
-        NTT_LARGE_CASES(CASE)
-#undef CASE
-        default:
-            return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
-                                uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
-                                uint32_t* singular) {
-    if (items == 0) return hipSuccess;
-    return wbits == 32 ? conv_fourstep_t<W32>(logn, f, g, h, items, item_stride, scratch, p, st, singular)
-                       : conv_fourstep_t<W64>(logn, f, g, h, items, item_stride, scratch, p, st, singular);
-}
-
-template <class W>
-static hipError_t ntt_fourstep_t(int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
-                                 const DevPlan& p, hipStream_t st) {
-    using T = typename W::word;
-    using SW = typename W::sword;
-    switch (logn) {
-#define CASE(n)                                                                                                   \
-    case n: {                                                                                                     \
-        using G = FS<n>;                                                                                          \
-        const uint64_t N = G::N;                                                                                  \
-        if (!inv) {                                                                                               \
-            hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st, (const T*)x,   \
-                               (SW*)scratch, N, N, p);                                                            \
-            hipLaunchKernelGGL((k_fs_row_fwd_nat<W, n>), dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,           \
-                               (const SW*)scratch, (T*)X, N, N, p);                                               \
-        } else {                                                                                                  \
-            hipLaunchKernelGGL((k_fs_row_inv_nat<W, n>), dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,           \
-                               (const T*)x, (SW*)scratch, N, N, p);                                               \
-            hipLaunchKernelGGL((k_fs_col_inv<W, n, true>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st,          \
-                               (const SW*)scratch, (T*)X, N, N, p);                                               \
-        }                                                                                                         \
-        return hipGetLastError();                                                                                 \
-    }
-        NTT_LARGE_CASES(CASE)
-#undef CASE
-        default:
-            return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
-                               const DevPlan& p, hipStream_t st) {
-    if (batch == 0) return hipSuccess;
-    return wbits == 32 ? ntt_fourstep_t<W32>(logn, inv, x, X, batch, scratch, p, st)
-                       : ntt_fourstep_t<W64>(logn, inv, x, X, batch, scratch, p, st);
-}
-
-template <class W>
-static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                               uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
-                               hipStream_t st) {
-    using T = typename W::word;
-    using SW = typename W::sword;
-    switch (logn) {
-#define CASE(n)                                                                                                   \
-    case n:                                                                                                       \
-        hipLaunchKernelGGL((k_conv_fused<W, n>), dim3(grid), dim3(FS<n>::T), 0, st, (const T*)f, (const T*)g, (T*)h, \
-                           offs, count, (SW*)scratch, queue, p);                                                  \
-        return hipGetLastError();
-        NTT_LARGE_CASES(CASE)
-#undef CASE
-        default:
-            return hipErrorInvalidValue;
-    }
-}
-
-template <class W>
-static hipError_t conv_multi_t(const void* f, const void* g, void* h, const void* tasks, uint32_t ntasks,
-                               const uint64_t* toffs, void* scratch, uint64_t scratch_words, uint32_t* queue,
-                               uint32_t grid, const DevPlan* plans, hipStream_t st) {
-    using T = typename W::word;
-    hipLaunchKernelGGL(k_conv_multi<W>, dim3(grid), dim3(512), 0, st, (const T*)f, (const T*)g, (T*)h,
-                       (const MultiTask*)tasks, ntasks, toffs, (typename W::sword*)scratch, scratch_words, queue,
-                       plans);
-    return hipGetLastError();
-}
-
-hipError_t launch_conv_multi(int wbits, const void* f, const void* g, void* h, const void* tasks, uint32_t ntasks,
-                             const uint64_t* toffs, void* scratch, uint64_t scratch_words, uint32_t* queue,
-                             uint32_t grid, const DevPlan* plans, hipStream_t st) {
-    if (ntasks == 0) return hipSuccess;
-    return wbits == 32 ? conv_multi_t<W32>(f, g, h, tasks, ntasks, toffs, scratch, scratch_words, queue, grid, plans, st)
-                       : conv_multi_t<W64>(f, g, h, tasks, ntasks, toffs, scratch, scratch_words, queue, grid, plans, st);
-}
-
-int multi_max_log2n(int wbits) { return wbits == 32 ? MultiCfg<W32>::NMAX : MultiCfg<W64>::NMAX; }
-int multi_tile(int logn) { return multi_s(1 << logn); }
-int multi_blocks_per_cu(int wbits) {
-    static std::atomic<int> cache[2] = {{-1}, {-1}};
-    std::atomic<int>& c = cache[wbits == 32 ? 0 : 1];
-    int v = c.load(std::memory_order_relaxed);
-    if (v < 0) {
-        int nb = 0;
-        const hipError_t e = wbits == 32
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_multi<W32>, 512, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_multi<W64>, 512, 0);
-        v = e == hipSuccess ? nb : 0;
-        c.store(v, std::memory_order_relaxed);
-    }
-    return v;
-}
-
-hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
-                             uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
-                             hipStream_t st) {
-    if (count == 0) return hipSuccess;
-    return wbits == 32 ? conv_fused_t<W32>(logn, f, g, h, offs, count, scratch, queue, grid, p, st)
-                       : conv_fused_t<W64>(logn, f, g, h, offs, count, scratch, queue, grid, p, st);
-}
-
-template <class W>
-static int fused_bpc_t(int logn) {
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (logn) {
-#define CASE(n) \
-    case n: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fused<W, n>, FS<n>::T, 0); break;
-        NTT_LARGE_CASES(CASE)
-#undef CASE
-        default:
-            break;
-    }
-    return e == hipSuccess ? nb : 0;
-}
-
-// Occupancy of the fused kernel, queried once per (word width, length) so that
-// later calls (also under graph capture) make no runtime query.
-int fused_blocks_per_cu(int wbits, int logn) {
-    // thread-safe one-time initialisation of the table (-1: not yet queried)
-    static std::atomic<int>* cache = [] {
-        auto* c = new std::atomic<int>[2 * (MAX_LOG2N + 1)];
-        for (int i = 0; i < 2 * (MAX_LOG2N + 1); ++i) c[i].store(-1);
-        return c;
-    }();
-    if (logn < 0 || logn > MAX_LOG2N) return 0;
-    std::atomic<int>& c = cache[(wbits == 32 ? 0 : MAX_LOG2N + 1) + logn];
-    int v = c.load(std::memory_order_relaxed);
-    if (v < 0) {
-        v = wbits == 32 ? fused_bpc_t<W32>(logn) : fused_bpc_t<W64>(logn);
-        c.store(v, std::memory_order_relaxed);
-    }
-    return v;
-}
-
-int fused_threads(int logn) {
-    switch (logn) {
-#define CASE(n) \
-    case n: return FS<n>::T;
-        NTT_LARGE_CASES(CASE)
-#undef CASE
-        default:
-            return 0;
-    }
 }
 
 }  // namespace nttmi
