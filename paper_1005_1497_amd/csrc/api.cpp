@@ -182,7 +182,7 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     Plan p;
     hipError_t he = upload(&p.dP, hP);
     if (he == hipSuccess && (int)log2n > SMALL_MAX_LOG2N) {
-        const int la = ((int)log2n + 1) / 2, lb = (int)log2n / 2;
+        const int la = fs_la((int)log2n), lb = (int)log2n - la;
         const uint64_t A = 1ull << la, B = 1ull << lb;
         std::vector<double> tt(N), tti(N);
         for (uint64_t u2 = 0; u2 < B; ++u2)

@@ -145,12 +145,12 @@ __global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, ty
 }
 
 // ------------------------------------------------------------------ four-step
-// Geometry for N = 2^LOGN = A * B, A = 2^ceil(LOGN/2) (row length),
-// B = 2^floor(LOGN/2) (column length).  Element t = t1 + A t2 (t1 < A, t2 < B),
+// Geometry for N = 2^LOGN = A * B, A = 2^fs_la(LOGN) (row length),
+// B = N / A (column length).  Element t = t1 + A t2 (t1 < A, t2 < B),
 // frequency u = u2 + B u1.  Scratch rows: Y[u2 * A + t1].
 template <int LOGN>
 struct FS {
-    static constexpr int la = (LOGN + 1) / 2, lb = LOGN / 2;
+    static constexpr int la = fs_la(LOGN), lb = LOGN - fs_la(LOGN);
     static constexpr int A = 1 << la, Bn = 1 << lb, N = 1 << LOGN;
     // threads per workgroup: 512, so that a column block of B = 256 spans 32
     // columns (128-byte rows of a block: whole cache lines)

@@ -20,6 +20,14 @@ struct DevPlan {
 };
 
 constexpr int SMALL_MAX_LOG2N = 12;
+// Four-step split of N = 2^n above 2^SMALL_MAX_LOG2N: N = A B with A = 2^fs_la(n)
+// (row length) and B = 2^(n - fs_la(n)) (column length).  Shared by the kernels
+// and the host tables of the twiddles w^(t1 u2).  Balanced up to 2^16; for
+// 2^17..2^19 the columns stay at 256 (two radix-16 passes, 32-column blocks of
+// whole cache lines) and the rows take the rest (measured 12-17% faster than
+// the balanced 512 x 512 and 1024 x 512 at 2^18 and 2^19); balanced again
+// above, where the row pass tables would no longer fit LDS.
+constexpr int fs_la(int n) { return (n >= 17 && n <= 19) ? n - 8 : (n + 1) / 2; }
 constexpr int MAX_LOG2N = 22;   // no prime below 2^24 has nu = 2^23; 64-bit words use the same kernels
 
 // wbits = 32 (uint32 words, m < 2^24) or 64 (uint64 words, m < 2^46).
