@@ -207,6 +207,53 @@ __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, i
     }
 }
 
+// Two independent length-L transforms of the same block geometry, pass by
+// pass in lockstep (va, vb as in block_dft_tw): the two register sets give the
+// scheduler independent work around each exchange, and the uniform twiddles
+// are loaded once.  The exchanges of va and vb take turns in `ldsbuf`.
+template <class W, int L, int S, int ORD, bool INV, class TWF>
+__device__ __forceinline__ void block_dft2_tw(double* va, double* vb, double* ldsbuf, int s, int j,
+                                              const double2* __restrict__ P, int lshift, int nmask,
+                                              const ModC& M, TWF twf) {
+    using B = Blk<L, S, ORD>;
+    constexpr int E = B::E;
+    asm volatile("" ::: "memory");
+    double2 twE[E / 2 > 0 ? E / 2 : 1];
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) twE[e] = ld_uniform(P, tw_index<INV>(e * (L / E), lshift, nmask));
+#pragma unroll
+    for (int vv = 0; vv < B::V0; ++vv) {
+        dft_reg<W, B::R0>(va + vv * B::R0, twE, E / B::R0, M);
+        dft_reg<W, B::R0>(vb + vv * B::R0, twE, E / B::R0, M);
+    }
+    int Ns = B::R0;
+#pragma unroll
+    for (int p = 1; p < B::NP; ++p) {
+        const int Rp = (p == 1) ? B::R0 : 16;
+        const int NsP = Ns / Rp;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            double* v = half ? vb : va;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int vv = i / Rp, r = i % Rp;
+                const int jv = j + vv * B::W;
+                const int pos = (jv / NsP) * NsP * Rp + (jv % NsP) + r * NsP;
+                ldsbuf[B::lds(s, pos)] = v[i];
+            }
+            xch_sync<B::WAVE_LOCAL>();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = ldsbuf[B::lds(s, j + r * (L / 16))];
+            xch_sync<B::WAVE_LOCAL>();
+        }
+        twf(va, p, Ns, j & (Ns - 1));
+        twf(vb, p, Ns, j & (Ns - 1));
+        dft_reg<W, 16>(va, twE, 1, M);
+        dft_reg<W, 16>(vb, twE, 1, M);
+        Ns *= 16;
+    }
+}
+
 // Per-pass twiddle tables of a length-L transform, laid out [pass][k][r] with
 // entry w_{16 Ns}^(r k) (k < Ns, r < 16), so that one work item's sixteen
 // twiddles are contiguous.  Rows are padded to 17 entries so that lanes with
