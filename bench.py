@@ -421,8 +421,10 @@ def variant_bench(args):
 def serve_bench(args):
     """Serving: Poisson arrivals of convolution requests, lengths 2^n with n
     uniform in [8, 18], m = 31065037602817 (64-bit words), continuous batching
-    over two streams; p50/p99 latency and throughput at offered load
-    rho * (saturated throughput), against one launch sequence per request."""
+    over four streams, at most a quarter of the arena per batch; p50/p99 latency and throughput at offered load
+    rho * (saturated throughput), with operands copied in at submission and
+    with zero-copy submission (operands already in pinned staging blocks),
+    against one launch sequence per request."""
     import threading
 
     import paper_1005_1497_amd.serve as sv
@@ -439,25 +441,45 @@ def serve_bench(args):
                                                          time.perf_counter() - t0))
     cap = 24   # 2^24 elements per arena (3 arenas x 128 MiB)
 
-    def run(reqs_, rate, max_batch):
-        ex = sv.GpuExecutor(m, capacity_log2=cap, elem_bits=64, streams=2)
-        srv = sv.ConvServer(ex, capacity_log2=cap, max_batch=max_batch, max_inflight=4).start()
-        for f, g in reqs_[:warm]:
-            srv.submit(f, g)
+    # zero-copy form: each request's operands already sit in a pinned staging
+    # block of the server (written there by the client before submission)
+    stager = sv.GpuExecutor(m, capacity_log2=0, elem_bits=64, streams=1)
+    t0 = time.perf_counter()
+    staged = []
+    for f, g in reqs:
+        blk = stager.staging(f.size)
+        bf, bg = stager.operand_views(blk)
+        bf[...] = f
+        bg[...] = g
+        staged.append((blk, int(f.size).bit_length() - 1))
+    log("staged %d requests in pinned blocks in %.1f s" % (len(staged), time.perf_counter() - t0))
+
+    def run(reqs_, rate, max_batch, zero_copy=False):
+        ex = sv.GpuExecutor(m, capacity_log2=cap, elem_bits=64, streams=4)
+        srv = sv.ConvServer(ex, capacity_log2=cap, max_batch=max_batch, max_inflight=4,
+                            max_batch_elems=1 << (cap - 2)).start()
+
+        def submit(i):
+            if zero_copy:
+                return srv.submit_staged(sv.StagedToken(*staged[i]))
+            return srv.submit(*reqs_[i])
+
+        for i in range(warm):
+            submit(i)
         srv.drain()
         srv.stats = sv.ServeStats()
-        body = reqs_[warm:]
+        body = range(warm, len(reqs_))
         gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
         t_start = time.perf_counter()
 
         def client():
             nxt = time.perf_counter()
-            for (f, g), gap in zip(body, gaps):
+            for i, gap in zip(body, gaps):
                 nxt += gap
                 d = nxt - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
-                srv.submit(f, g)
+                submit(i)
 
         th = threading.Thread(target=client)
         th.start()
@@ -475,6 +497,12 @@ def serve_bench(args):
     rate = args.rho * sat["throughput_conv_per_s"]
     served = run(reqs, rate, 512)
     log("served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (rate, served["p50_ms"], served["p99_ms"]))
+    zc_sat = run(reqs, None, 512, zero_copy=True)
+    log("zero-copy closed loop: %.0f conv/s" % zc_sat["throughput_conv_per_s"])
+    zc_rate = args.rho * zc_sat["throughput_conv_per_s"]
+    zc = run(reqs, zc_rate, 512, zero_copy=True)
+    log("zero-copy served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (zc_rate, zc["p50_ms"], zc["p99_ms"]))
+    zc_same = run(reqs, rate, 512, zero_copy=True)
     single_sat = run(reqs, None, 1)
     single = run(reqs, args.rho * single_sat["throughput_conv_per_s"], 1)
     single_at_rate = run(reqs, rate, 1) if rate <= single_sat["throughput_conv_per_s"] else None
@@ -484,9 +512,11 @@ def serve_bench(args):
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
         "latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"]},
         "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "rho": args.rho, "offered_per_s": rate,
-                   "words": "u64", "streams": 2},
+                   "words": "u64", "streams": 4,
+                   "max_batch_elems": 1 << (cap - 2)},
         "saturated": sat, "served": served,
-        "forms": {"one_launch_per_request_saturated": single_sat, "one_launch_per_request_at_rho": single,
+        "forms": {"zero_copy_saturated": zc_sat, "zero_copy_at_rho": zc, "zero_copy_at_same_rate": zc_same,
+                  "one_launch_per_request_saturated": single_sat, "one_launch_per_request_at_rho": single,
                   "one_launch_per_request_at_same_rate": single_at_rate},
     }
     print(json.dumps(out), flush=True)

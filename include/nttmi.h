@@ -190,6 +190,20 @@ ntt_status ntt_max_log2n(uint64_t m, uint32_t *log2n);
  * non-residue z.  Writes it to *root. */
 ntt_status ntt_euler_root(uint64_t m, uint32_t log2n, uint64_t *root);
 
+/* Staging helper for the served form (plumbing, no arithmetic of the method):
+ * enqueues count asynchronous copies dst[i] <- src[i] of bytes[i] bytes on
+ * `stream`, in index order, with hipMemcpyDefault (each side device memory or
+ * pinned host memory), so that a batch of requests is uploaded or downloaded
+ * in one call rather than one per request.  dst, src and bytes are host arrays
+ * of count entries owned by the caller and read before the call returns; the
+ * buffers they point to must stay valid until the stream has run the copies.
+ * A zero-byte entry is skipped.  NTT_E_ARG: a null array with count > 0, or a
+ * null pointer in an entry of non-zero size (nothing is enqueued then);
+ * NTT_E_DEVICE: the runtime refused a copy (the copies before it stay
+ * enqueued). */
+ntt_status ntt_copy_batch(void *const *dst, const void *const *src, const uint64_t *bytes, uint32_t count,
+                          void *stream);
+
 /* Static description of a status code. */
 const char *ntt_status_string(ntt_status s);
 

@@ -18,13 +18,14 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 __all__ = [
     "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt", "conv2d",
     "default_root", "modulus_order", "release_caches", "status_string",
     "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "STATUS",
-    "euler_root", "max_log2n",
+    "euler_root", "max_log2n", "copy_batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -89,6 +90,8 @@ def _load():
     L.ntt_max_log2n.restype = I32
     L.ntt_euler_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
     L.ntt_euler_root.restype = I32
+    L.ntt_copy_batch.argtypes = [VP, VP, VP, U32, VP]
+    L.ntt_copy_batch.restype = I32
     L.ntt_status_string.argtypes = [I32]
     L.ntt_status_string.restype = ctypes.c_char_p
     L.ntt_release_caches.argtypes = []
@@ -286,6 +289,17 @@ class BatchDesc:
         self.c = _BatchDesc(len(self.log2n),
                             self.log2n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                             self.offset.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+
+
+def copy_batch(dst, src, nbytes, stream=None) -> None:
+    """Enqueues the copies dst[i] <- src[i] of nbytes[i] bytes on ``stream`` in
+    one library call (device or pinned host addresses, as integers)."""
+    d = np.ascontiguousarray(dst, dtype=np.uint64)
+    s_ = np.ascontiguousarray(src, dtype=np.uint64)
+    b = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    if not (d.ndim == s_.ndim == b.ndim == 1) or not (d.size == s_.size == b.size):
+        raise ValueError("dst, src and nbytes must be 1-D of one length")
+    _check(lib.ntt_copy_batch(d.ctypes.data, s_.ctypes.data, b.ctypes.data, d.size, _stream(stream)), "ntt_copy_batch")
 
 
 def conv_batched(f: torch.Tensor, g: torch.Tensor, desc, m: int, root: int = 2, root_log2order: int | None = None,

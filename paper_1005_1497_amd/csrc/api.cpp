@@ -921,6 +921,21 @@ ntt_status ntt_modulus_order(uint64_t m, uint32_t* log2_nu) {
     return NTT_OK;
 }
 
+ntt_status ntt_copy_batch(void* const* dst, const void* const* src, const uint64_t* bytes, uint32_t count,
+                          void* stream) {
+    if (count == 0) return NTT_OK;
+    if (!dst || !src || !bytes) return NTT_E_ARG;
+    for (uint32_t i = 0; i < count; ++i)
+        if (bytes[i] && (!dst[i] || !src[i])) return NTT_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!bytes[i]) continue;
+        hipError_t e = hipMemcpyAsync(dst[i], src[i], (size_t)bytes[i], hipMemcpyDefault, s);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return NTT_OK;
+}
+
 const char* ntt_status_string(ntt_status s) {
     switch (s) {
         case NTT_OK: return "ok";

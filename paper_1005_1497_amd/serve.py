@@ -12,6 +12,13 @@ Requests (f, g) of power-of-two lengths arrive at any time.  A scheduler thread
   3. copies each result back, completes the request's future and frees its
      slot, which lets further requests in.
 
+A request enters either by submit(f, g), which copies the operands into a pinned
+staging buffer of the executor, or without that host copy: buffers(n) hands out
+the staging buffer's operand rows, the caller writes f and g there in place and
+passes the token to submit_staged().  Results are host arrays over the request's
+pinned result row (no copy after the download); each stays valid while the
+caller holds it.
+
 Operands stay resident in the arenas from admission to completion.  Latency is
 completion time minus arrival time on the host monotonic clock.
 
@@ -114,8 +121,22 @@ class ServeStats:
         return float(np.percentile(np.array(self.latencies), q)) if self.latencies else float("nan")
 
 
+@dataclass
+class StagedToken:
+    """A staging buffer handed out by ConvServer.buffers, not yet submitted."""
+    staged: object
+    log2n: int
+    used: bool = False
+
+
 class GpuExecutor:
-    """Device side of the server: arenas, streams and conv_batched launches."""
+    """Device side of the server: arenas, streams and conv_batched launches.
+
+    Executor protocol (ConvServer calls only these): staging(n) -> a staging
+    object for one request of length n; operand_views(staged) -> writable host
+    arrays (f, g) inside it; prepare(f, g) -> a filled staging object;
+    launch(requests, stream_id) -> handle; poll(handle) -> bool;
+    results(handle) -> one host array per request; streams."""
 
     def __init__(self, m: int, capacity_log2: int, elem_bits: int = 64, streams: int = 2, device: int = 0,
                  root: int = 2, root_log2order: int | None = None):
@@ -128,21 +149,32 @@ class GpuExecutor:
         self.np_dtype = np.uint64 if elem_bits == 64 else np.uint32
         self.dev = torch.device("cuda", device)
         n = 1 << capacity_log2
-        self.F = torch.zeros(n, dtype=self.dtype, device=self.dev)
-        self.G = torch.zeros(n, dtype=self.dtype, device=self.dev)
-        self.H = torch.zeros(n, dtype=self.dtype, device=self.dev)
+        # arenas: slots are written by uploads before any kernel reads them
+        self.F = torch.empty(n, dtype=self.dtype, device=self.dev)
+        self.G = torch.empty(n, dtype=self.dtype, device=self.dev)
+        self.H = torch.empty(n, dtype=self.dtype, device=self.dev)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
+        self.wb = elem_bits // 8
+        self.F_ptr, self.G_ptr, self.H_ptr = (np.uint64(t.data_ptr()) for t in (self.F, self.G, self.H))
         self.root = root
         self.rlo = root_log2order if root_log2order is not None else nt.modulus_order(m)
+
+    def staging(self, n: int):
+        """One pinned host block of rows f, g and the result for a request of
+        length n."""
+        return self.torch.empty((3, n), dtype=self.dtype, pin_memory=True)
+
+    def operand_views(self, staged):
+        v = staged.numpy().view(self.np_dtype)
+        return v[0], v[1]
 
     def prepare(self, f: np.ndarray, g: np.ndarray):
         """Runs on the submitting thread: pinned host copies of the operands
         and a pinned buffer for the result."""
-        n = f.size
-        t = self.torch.empty((3, n), dtype=self.dtype, pin_memory=True)
-        v = t.numpy().view(self.np_dtype)
-        v[0] = f
-        v[1] = g
+        t = self.staging(f.size)
+        vf, vg = self.operand_views(t)
+        vf[...] = f
+        vg[...] = g
         return t
 
     def launch(self, reqs, stream_id: int):
@@ -150,36 +182,51 @@ class GpuExecutor:
         results out; returns a handle to poll."""
         torch, nt = self.torch, self.nt
         s = self.streams[stream_id]
+        k = len(reqs)
+        off = np.fromiter((r.offset for r in reqs), np.uint64, k)
+        lg = np.fromiter((r.log2n for r in reqs), np.uint64, k)
+        host = np.fromiter((r.staged.data_ptr() for r in reqs), np.uint64, k)
+        nb = (np.uint64(1) << lg) * np.uint64(self.wb)                  # bytes of one row
+        dev_off = off * np.uint64(self.wb)
+        # one library call uploads every request's f and g rows, one downloads h
+        up_dst = np.concatenate([self.F_ptr + dev_off, self.G_ptr + dev_off])
+        up_src = np.concatenate([host, host + nb])
+        down_dst = host + nb * np.uint64(2)
+        down_src = self.H_ptr + dev_off
         with torch.cuda.stream(s):
-            for r in reqs:
-                N = 1 << r.log2n
-                self.F[r.offset:r.offset + N].copy_(r.staged[0], non_blocking=True)
-                self.G[r.offset:r.offset + N].copy_(r.staged[1], non_blocking=True)
-            desc = nt.BatchDesc([r.log2n for r in reqs], [r.offset for r in reqs])
+            nt.copy_batch(up_dst, up_src, np.concatenate([nb, nb]), stream=s)
+            desc = nt.BatchDesc(lg.astype(np.uint8), off)
             nt.conv_batched(self.F, self.G, desc, self.m, root=self.root, root_log2order=self.rlo, out=self.H,
                             stream=s)
-            for r in reqs:
-                N = 1 << r.log2n
-                r.staged[2].copy_(self.H[r.offset:r.offset + N], non_blocking=True)
+            nt.copy_batch(down_dst, down_src, nb, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
+        # the staging blocks stay referenced by the handle until the event has
+        # passed, and afterwards by the result arrays
         return (ev, [r.staged for r in reqs], desc)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def results(self, handle):
-        return [t[2].numpy().view(self.np_dtype).copy() for t in handle[1]]
+        # views of the pinned result rows: the staging block lives as long as
+        # the caller keeps the array
+        return [t[2].numpy().view(self.np_dtype) for t in handle[1]]
 
 
 class ConvServer:
     """Continuous-batching server over an executor (see module docstring)."""
 
     def __init__(self, executor, capacity_log2: int, min_log2: int = 0, max_batch: int = 512,
-                 max_inflight: int = 4):
+                 max_inflight: int = 4, max_batch_elems: int | None = None):
+        """max_batch caps the requests of one launch; max_batch_elems caps its
+        arena elements (a single larger request still goes alone), so that
+        several batches fit in the arena at once and the uploads of one
+        overlap the work of another."""
         self.ex = executor
         self.alloc = BuddyAllocator(capacity_log2, min_log2)
         self.max_batch = max_batch
+        self.max_batch_elems = max_batch_elems
         self.max_inflight = max_inflight
         self.queue = collections.deque()
         self.inflight = []
@@ -194,15 +241,39 @@ class ConvServer:
         self.admission_log = []     # request ids in admission order
 
     # ------------------------------------------------------------ client side
-    def submit(self, f: np.ndarray, g: np.ndarray) -> concurrent.futures.Future:
-        if f.shape != g.shape or f.ndim != 1 or f.size == 0 or f.size & (f.size - 1):
-            raise ValueError("f and g must be 1-D of the same power-of-two length")
-        log2n = int(f.size).bit_length() - 1
+    def _log2_len(self, n: int) -> int:
+        if n <= 0 or n & (n - 1):
+            raise ValueError("request length must be a power of two")
+        log2n = int(n).bit_length() - 1
         if log2n > self.alloc.total_log2:
             raise ValueError("request larger than the device arena")
-        fut = concurrent.futures.Future()
+        return log2n
+
+    def submit(self, f: np.ndarray, g: np.ndarray) -> concurrent.futures.Future:
+        if f.shape != g.shape or f.ndim != 1:
+            raise ValueError("f and g must be 1-D of the same power-of-two length")
+        log2n = self._log2_len(f.size)
         arrival = time.monotonic()
-        staged = self.ex.prepare(f, g)
+        return self._enqueue(self.ex.prepare(f, g), log2n, arrival)
+
+    def buffers(self, n: int):
+        """Zero-copy submission, first half: returns (f, g, token), where f and g
+        are writable host arrays of length n inside a staging buffer.  Fill
+        them, then call submit_staged(token) once."""
+        log2n = self._log2_len(n)
+        staged = self.ex.staging(n)
+        f, g = self.ex.operand_views(staged)
+        return f, g, StagedToken(staged, log2n)
+
+    def submit_staged(self, token: StagedToken) -> concurrent.futures.Future:
+        """Zero-copy submission, second half: enqueues the filled buffer."""
+        if token.used:
+            raise ValueError("staging token already submitted")
+        token.used = True
+        return self._enqueue(token.staged, token.log2n, time.monotonic())
+
+    def _enqueue(self, staged, log2n: int, arrival: float) -> concurrent.futures.Future:
+        fut = concurrent.futures.Future()
         with self._lock:
             r = Request(self._rid, staged, log2n, arrival, fut)
             self._rid += 1
@@ -252,13 +323,18 @@ class ConvServer:
     def _admit(self):
         """Admits queued requests in arrival order while slots are free."""
         admitted = []
+        elems = 0
         while self.queue and len(admitted) < self.max_batch:
             r = self.queue[0]
+            size = 1 << max(r.log2n, self.alloc.min_log2)
+            if admitted and self.max_batch_elems is not None and elems + size > self.max_batch_elems:
+                break
             off = self.alloc.alloc(r.log2n)
             if off is None:
                 break
             self.queue.popleft()
             r.offset = off
+            elems += size
             admitted.append(r)
             self.admission_log.append(r.rid)
         self.stats.peak_used = max(self.stats.peak_used, self.alloc.used)

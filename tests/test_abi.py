@@ -45,6 +45,8 @@ def lib():
     L.ntt_max_log2n.restype = I32
     L.ntt_euler_root.argtypes = [U64, U32, ctypes.POINTER(U64)]
     L.ntt_euler_root.restype = I32
+    L.ntt_copy_batch.argtypes = [VP, VP, VP, U32, VP]
+    L.ntt_copy_batch.restype = I32
     L.ntt_status_string.argtypes = [I32]
     L.ntt_status_string.restype = ctypes.c_char_p
     return L
@@ -184,3 +186,15 @@ def test_conv2d_validation(lib):
     assert c(M, 10, 4, r10, r10, 32, BAD, BAD, H, 0, None) == 4               # column root of the wrong order
     assert c(M, 10, 4, r10, r4, 32, None, BAD, H, 0, None) == 1               # null
     assert c(M, 10, 4, r10, r4, 32, BAD, BAD, ctypes.c_void_p(0x100000 + 64), 0, None) == 1   # overlap
+
+
+def test_copy_batch_validation(lib):
+    # host-side checks only: nothing reaches the runtime
+    import numpy as np
+    z = np.zeros(2, np.uint64)
+    assert lib.ntt_copy_batch(None, None, None, 0, None) == 0          # nothing to copy
+    assert lib.ntt_copy_batch(None, z.ctypes.data, z.ctypes.data, 2, None) == 1
+    dst = np.array([0x1000, 0], np.uint64)
+    src = np.array([0x2000, 0x3000], np.uint64)
+    nb = np.array([8, 8], np.uint64)                                      # entry 1 has a null dst
+    assert lib.ntt_copy_batch(dst.ctypes.data, src.ctypes.data, nb.ctypes.data, 2, None) == 1

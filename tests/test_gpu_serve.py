@@ -39,3 +39,33 @@ def test_served_equals_alone(bits, m):
         f, g = reqs[k]
         idx = np.array([0, f.size - 1])
         assert np.array_equal(futs[k].result()[idx], oracle.conv_entries(f, g, m, idx).astype(dt))
+
+
+def test_zero_copy_submission_and_result_lifetime():
+    # operands written in place into the executor's pinned staging rows; the
+    # results are views of pinned rows and must stay intact after later batches
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import ConvServer, GpuExecutor
+    m = si.M_U64
+    rng = np.random.default_rng(17)
+    lens = si.served_lengths(120, seed=8)
+    ex = GpuExecutor(m, capacity_log2=21, elem_bits=64, streams=2)
+    srv = ConvServer(ex, capacity_log2=21, max_inflight=4).start()
+    ops, futs = [], []
+    for n in lens:
+        N = 1 << int(n)
+        bf, bg, tok = srv.buffers(N)
+        bf[...] = rng.integers(0, m, N, dtype=np.uint64)
+        bg[...] = rng.integers(0, m, N, dtype=np.uint64)
+        ops.append((bf.copy(), bg.copy()))
+        futs.append(srv.submit_staged(tok))
+    first = [fu.result() for fu in futs[:10]]
+    snap = [a.copy() for a in first]
+    for f, g in ops[:40]:                       # more batches after the first results
+        srv.submit(f, g)
+    srv.drain()
+    srv.stop()
+    for a, b in zip(first, snap):
+        assert np.array_equal(a, b)
+    for (f, g), fu in zip(ops, futs):
+        assert np.array_equal(fu.result(), host(nt.conv_circular(dev(f), dev(g), m)))

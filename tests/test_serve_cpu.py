@@ -50,6 +50,12 @@ class FakeExecutor:
         self.fail_on = fail_on
         self.launches = []
 
+    def staging(self, n):
+        return (np.zeros(n, np.uint64), np.zeros(n, np.uint64))
+
+    def operand_views(self, staged):
+        return staged
+
     def prepare(self, f, g):
         return (np.array(f, dtype=np.uint64), np.array(g, dtype=np.uint64))
 
@@ -161,3 +167,39 @@ def test_rejects_bad_requests():
         srv.submit(np.zeros(6, np.uint64), np.zeros(6, np.uint64))
     with pytest.raises(ValueError):
         srv.submit(np.zeros(64, np.uint64), np.zeros(64, np.uint64))
+
+
+def test_zero_copy_submission():
+    ex = FakeExecutor(M)
+    srv = ConvServer(ex, capacity_log2=9).start()
+    reqs = _reqs(40, seed=9)
+    futs = []
+    for f, g in reqs:
+        bf, bg, tok = srv.buffers(f.size)
+        bf[...] = f
+        bg[...] = g
+        futs.append(srv.submit_staged(tok))
+        with pytest.raises(ValueError):
+            srv.submit_staged(tok)          # a token is submitted once
+    srv.stop()
+    for (f, g), fu in zip(reqs, futs):
+        assert np.array_equal(fu.result(), oracle.conv_direct(f, g, M))
+    for bad in (0, 12, 1024):
+        with pytest.raises(ValueError):
+            srv.buffers(bad)
+
+
+def test_batch_element_cap():
+    ex = FakeExecutor(M, delay=0.001)
+    srv = ConvServer(ex, capacity_log2=10, max_batch_elems=256)
+    reqs = _reqs(60, seed=4, lo=3, hi=9)                 # up to 512 elements: above the cap
+    futs = [srv.submit(f, g) for f, g in reqs]
+    srv.start()
+    srv.stop()
+    sizes = {r: f.size for r, (f, _) in enumerate(reqs)}
+    for batch in ex.launches:
+        total = sum(sizes[r] for r in batch)
+        assert total <= 256 or len(batch) == 1
+    assert [r for b in ex.launches for r in b] == list(range(60))     # arrival order kept
+    for (f, g), fu in zip(reqs, futs):
+        assert np.array_equal(fu.result(), oracle.conv_direct(f, g, M))
