@@ -149,3 +149,32 @@ def test_autotuned_form_matches(nt, lengths):
     fd = dev(f)
     nt.conv_batched(fd, dev(g), desc, M, out=fd, flags=nt.FLAG_AUTOTUNE)
     assert np.array_equal(host(fd), ref)
+
+
+def test_full_size_batch_in_bench_configuration(nt):
+    # the timed workload itself: 4096 x N = 2^16 through the persistent fused
+    # launch.  Every item is checked through its values at the roots of unity
+    # x = 1 and x = -1 (h(x) = f(x) g(x) for x^N = 1, which holds at any size);
+    # sampled entries of a few items against the oracle's direct sum.
+    w = si.batch_n65536(4096)
+    n, count, N = 16, 4096, 1 << 16
+    f, g = si.operands(w)
+    desc = nt.BatchDesc([n] * count, si.offsets([n] * count))
+    h = host(nt.conv_batched(dev(f), dev(g), desc, M)).reshape(count, N).astype(np.int64)
+    F = f.reshape(count, N).astype(np.int64)
+    G = g.reshape(count, N).astype(np.int64)
+
+    def at_one(x):
+        return x.sum(axis=1) % M
+
+    def at_minus_one(x):
+        return (x[:, 0::2].sum(axis=1) - x[:, 1::2].sum(axis=1)) % M
+
+    assert np.array_equal(at_one(h), at_one(F) * at_one(G) % M)
+    assert np.array_equal(at_minus_one(h), at_minus_one(F) * at_minus_one(G) % M)
+    assert h.max() < M and h.min() >= 0
+    rng = np.random.default_rng(99)
+    for i in (0, 1, 2047, count - 1, int(rng.integers(0, count))):
+        idx = np.unique(np.r_[0, N - 1, rng.integers(0, N, 8)])
+        ref = oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], M, idx)
+        assert np.array_equal(h[i, idx], ref.astype(np.int64)), i
