@@ -381,7 +381,8 @@ class ConvServer:
                         self.inflight.remove(b)
                         self._complete(b)
             if not admitted and not done:
+                # nothing to launch or complete: sleep until a submission or the
+                # next poll of the batches in flight (never spin on the lock)
                 with self._lock:
-                    if not self._stop and (not self.queue or len(self.inflight) >= self.max_inflight
-                                           or self.alloc.used == self.alloc.capacity):
+                    if not self._stop:
                         self._wake.wait(timeout=0.0002)
