@@ -183,6 +183,11 @@ class GpuExecutor:
         torch, nt = self.torch, self.nt
         s = self.streams[stream_id]
         k = len(reqs)
+        for r in reqs:        # the copies below address whole staging blocks by raw pointer
+            t = r.staged
+            if tuple(t.shape) != (3, 1 << r.log2n) or t.dtype != self.dtype or not t.is_contiguous():
+                raise ValueError("request %d: staging block is not a (3, %d) block of this executor"
+                                 % (r.rid, 1 << r.log2n))
         off = np.fromiter((r.offset for r in reqs), np.uint64, k)
         lg = np.fromiter((r.log2n for r in reqs), np.uint64, k)
         host = np.fromiter((r.staged.data_ptr() for r in reqs), np.uint64, k)
