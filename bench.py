@@ -10,6 +10,7 @@ Prints one JSON line (see the README for the fields); diagnostic lines go to
 stderr.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -489,6 +490,10 @@ def serve_bench(args):
         srv.stats = sv.ServeStats()
         body = range(warm, len(reqs_))
         gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
+        # the set-up objects (drawn requests, staging blocks) are long-lived:
+        # keep the cyclic collector from walking them during the timed run
+        gc.collect()
+        gc.freeze()
         t_start = time.perf_counter()
 
         def client():

@@ -78,6 +78,15 @@ typedef enum {
                                         2^v, 2^v the largest power of two dividing m - 1
                                         (ntt_max_log2n).  conv_batched:
                                         root_log2order <= v */
+#define NTT_FLAG_TRANSIENT     0x20u /* conv_batched: the descriptor is used once (a
+                                        served batch).  Its device copy goes through a
+                                        per-stream ring of staging slots, uploaded on
+                                        the stream, instead of the content-addressed
+                                        descriptor cache, so a stream of distinct
+                                        batches never evicts that cache (which
+                                        synchronises the device).  Ignored while the
+                                        stream is being captured (captured kernels need
+                                        descriptors that later calls do not overwrite) */
 
 /* Batch of independent convolutions of uneven power-of-two lengths.
  * Item i has length N_i = 2^log2n[i] and occupies elements

@@ -24,7 +24,7 @@ import torch
 __all__ = [
     "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt", "conv2d",
     "default_root", "modulus_order", "release_caches", "status_string",
-    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "STATUS",
+    "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "FLAG_TRANSIENT", "STATUS",
     "euler_root", "max_log2n", "copy_batch",
 ]
 
@@ -40,6 +40,7 @@ FLAG_PER_ITEM = 0x2
 FLAG_PER_CLASS = 0x4
 FLAG_AUTOTUNE = 0x8
 FLAG_EULER = 0x10
+FLAG_TRANSIENT = 0x20
 
 EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "conv_crt",
            "conv2d_circular",

@@ -46,6 +46,24 @@ struct BatchForm {
     std::map<uint32_t, uint8_t> cls;   // log2n -> ClassForm
 };
 
+// Staging ring of transient descriptors on one stream.  Slot k owns a pinned
+// host buffer and a device buffer; an upload waits for the slot's previous
+// host-to-device copy (its event), fills the host buffer and enqueues the copy
+// on the stream.  Kernels that read the device buffer run on the same stream,
+// so the slot's next copy is ordered after them.
+constexpr int RING_SLOTS = 8;
+struct RingSlot {
+    void* dev = nullptr;
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+};
+struct Ring {
+    std::mutex mu;   // serialises uploads on the stream (the cache lock is not held while waiting)
+    RingSlot slot[RING_SLOTS];
+    unsigned next = 0;
+};
+
 struct Caches {
     std::mutex mu;
     std::map<std::tuple<int, uint64_t, int, uint64_t>, Plan> plans;   // (dev, m, log2n, root)
@@ -55,6 +73,7 @@ struct Caches {
     std::map<std::pair<int, void*>, Buf> tune;                        // (dev, stream) -> autotuning output
     std::map<std::vector<uint64_t>, struct BatchForm> forms;          // batch shape -> tuned form
     std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
+    std::map<std::pair<int, void*>, struct Ring> rings;               // (dev, stream) -> transient uploads
     std::map<uint64_t, std::pair<int, int>> moduli;                   // m -> (log2 nu or -1, v2(m-1) or -1)
     std::map<int, int> cu_count;                                      // dev -> CUs
 };
@@ -305,6 +324,61 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out) {
     return NTT_OK;
 }
 
+// Device copy of a descriptor used by one call: through the stream's staging
+// ring when `transient` and the stream is not being captured, else through the
+// content-addressed cache above.
+ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream, const uint64_t** out) {
+    if (transient) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return NTT_E_DEVICE;
+        transient = cs == hipStreamCaptureStatusNone;
+    }
+    if (!transient) return get_offsets(h, out);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = std::max<size_t>(8, h.size() * sizeof(uint64_t));
+    Caches& c = caches();
+    Ring* rp = nullptr;
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        rp = &c.rings[std::make_pair(dev, stream)];   // map nodes stay put
+    }
+    Ring& r = *rp;
+    std::lock_guard<std::mutex> g(r.mu);
+    RingSlot& sl = r.slot[r.next++ % RING_SLOTS];
+    hipError_t e = hipSuccess;
+    if (sl.ev) e = hipEventSynchronize(sl.ev);          // the slot's previous copy has run
+    else e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_status(e);
+    if (sl.cap < bytes) {
+        if (sl.dev) {
+            // kernels enqueued earlier on this stream may still read the old buffer
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_status(e);
+            (void)hipFree(sl.dev);
+            (void)hipHostFree(sl.host);
+            sl.dev = sl.host = nullptr;
+            sl.cap = 0;
+        }
+        const size_t cap = std::max<size_t>(bytes, 4096);
+        e = hipMalloc(&sl.dev, cap);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (sl.dev) (void)hipFree(sl.dev);
+            sl.dev = sl.host = nullptr;
+            return hip_status(e);
+        }
+        sl.cap = cap;
+    }
+    std::memcpy(sl.host, h.data(), h.size() * sizeof(uint64_t));
+    e = hipMemcpyAsync(sl.dev, sl.host, h.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(sl.ev, s);
+    if (e != hipSuccess) return hip_status(e);
+    *out = (const uint64_t*)sl.dev;
+    return NTT_OK;
+}
+
 int cu_count() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -399,7 +473,7 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
 // the persistent fused four-step kernel above.
 ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan* p, uint32_t elem_bits,
                         const char* F, const char* G, char* H, hipStream_t s, void* stream,
-                        uint8_t form = CF_DEFAULT) {
+                        uint8_t form = CF_DEFAULT, bool transient = false) {
     const size_t wb = elem_bits / 8;
     const uint32_t c = (uint32_t)off.size();
     // contiguous uniform run: offsets base + i N, no table needed
@@ -409,7 +483,7 @@ ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan
     const uint64_t* doffs = nullptr;
     ntt_status st = NTT_OK;
     if (!contiguous) {
-        st = get_offsets(off, &doffs);
+        st = get_desc(off, transient, stream, &doffs);
         if (st != NTT_OK) return st;
     }
     if ((int)n <= SMALL_MAX_LOG2N)
@@ -451,7 +525,7 @@ ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan
 // distinct batch and cached by content.
 ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
                         std::map<uint32_t, const Plan*>& plans, uint32_t nmax, uint32_t elem_bits, const char* F,
-                        const char* G, char* H, hipStream_t s, void* stream) {
+                        const char* G, char* H, hipStream_t s, void* stream, bool transient = false) {
     std::vector<uint64_t> toffs;
     std::vector<uint64_t> tasks;   // two words per task: first item; log2n | count << 32
     uint32_t nbig = 0;
@@ -473,20 +547,31 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
     std::vector<uint64_t> blob(toffs);
     const size_t task_at = blob.size();
     blob.insert(blob.end(), tasks.begin(), tasks.end());
-    const uint64_t* dblob = nullptr;
-    ntt_status st = get_offsets(blob, &dblob);
-    if (st != NTT_OK) return st;
     // per-length plans, indexed by log2n
-    static_assert(sizeof(DevPlan) % 8 == 0, "DevPlan is uploaded as 8-byte words");
+    static_assert(sizeof(DevPlan) % 8 == 0 && alignof(DevPlan) <= 16, "DevPlan is uploaded as 8-byte words");
     std::vector<DevPlan> hp(nmax + 1);
     std::memset((void*)hp.data(), 0, hp.size() * sizeof(DevPlan));
     for (auto& kv : plans)
         if (kv.first <= nmax) hp[kv.first] = kv.second->dev;
     std::vector<uint64_t> pw(hp.size() * sizeof(DevPlan) / 8);
     std::memcpy(pw.data(), hp.data(), pw.size() * 8);
+    const uint64_t* dblob = nullptr;
     const uint64_t* dplans = nullptr;
-    st = get_offsets(pw, &dplans);
-    if (st != NTT_OK) return st;
+    ntt_status st = NTT_OK;
+    if (transient) {
+        // one upload: items and tasks, padded to 16 bytes, then the plans
+        const size_t plans_at = (blob.size() + 1) & ~(size_t)1;
+        blob.resize(plans_at, 0);
+        blob.insert(blob.end(), pw.begin(), pw.end());
+        st = get_desc(blob, true, stream, &dblob);
+        if (st != NTT_OK) return st;
+        dplans = dblob + plans_at;
+    } else {
+        st = get_offsets(blob, &dblob);
+        if (st != NTT_OK) return st;
+        st = get_offsets(pw, &dplans);
+        if (st != NTT_OK) return st;
+    }
     const size_t wb = elem_bits / 8;
     const uint64_t scratch_words = nbig ? (2ull << nbig) : 1;
     uint64_t grid = (uint64_t)std::max(1, cu_count()) * std::max(1, multi_blocks_per_cu((int)elem_bits));
@@ -505,17 +590,17 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
 // Runs a batch in the given form.
 ntt_status run_batch(const BatchForm& form, const std::map<uint32_t, std::vector<uint64_t>>& cls,
                      std::map<uint32_t, const Plan*>& plans, uint32_t nmax, uint32_t elem_bits, const char* F,
-                     const char* G, char* H, hipStream_t s, void* stream) {
+                     const char* G, char* H, hipStream_t s, void* stream, bool transient = false) {
     ntt_status st = NTT_OK;
     if (form.multi) {
-        st = launch_multi(cls, plans, nmax, elem_bits, F, G, H, s, stream);
+        st = launch_multi(cls, plans, nmax, elem_bits, F, G, H, s, stream, transient);
         if (st != NTT_OK) return st;
     }
     for (auto& kv : cls) {
         if (form.multi && kv.first <= nmax) continue;
         auto it = form.cls.find(kv.first);
         const uint8_t cf = it == form.cls.end() ? (uint8_t)CF_DEFAULT : it->second;
-        st = launch_class(kv.first, kv.second, plans[kv.first], elem_bits, F, G, H, s, stream, cf);
+        st = launch_class(kv.first, kv.second, plans[kv.first], elem_bits, F, G, H, s, stream, cf, transient);
         if (st != NTT_OK) return st;
     }
     return NTT_OK;
@@ -879,7 +964,7 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
         store_form(key, form);
     }
     if (flags & NTT_FLAG_PER_CLASS) form.multi = false;
-    return run_batch(form, cls, plans, nmax, elem_bits, F, G, H, s, stream);
+    return run_batch(form, cls, plans, nmax, elem_bits, F, G, H, s, stream, (flags & NTT_FLAG_TRANSIENT) != 0);
 }
 
 ntt_status ntt_default_root(uint64_t m, uint32_t log2n, uint64_t* root) {
@@ -975,6 +1060,13 @@ void ntt_release_caches(void) {
     c.forms.clear();
     for (auto& kv : c.offsets) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     c.offsets.clear();
+    for (auto& kv : c.rings)
+        for (RingSlot& sl : kv.second.slot) {
+            if (sl.dev) (void)hipFree(sl.dev);
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.ev) (void)hipEventDestroy(sl.ev);
+        }
+    c.rings.clear();
 }
 
 }  // extern "C"

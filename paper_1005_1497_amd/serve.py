@@ -201,8 +201,9 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             nt.copy_batch(up_dst, up_src, np.concatenate([nb, nb]), stream=s)
             desc = nt.BatchDesc(lg.astype(np.uint8), off)
+            # a served batch's descriptor is used once: the stream's staging ring
             nt.conv_batched(self.F, self.G, desc, self.m, root=self.root, root_log2order=self.rlo, out=self.H,
-                            stream=s)
+                            flags=nt.FLAG_TRANSIENT, stream=s)
             nt.copy_batch(down_dst, down_src, nb, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)

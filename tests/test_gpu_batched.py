@@ -178,3 +178,40 @@ def test_full_size_batch_in_bench_configuration(nt):
         idx = np.unique(np.r_[0, N - 1, rng.integers(0, N, 8)])
         ref = oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], M, idx)
         assert np.array_equal(h[i, idx], ref.astype(np.int64)), i
+
+
+def test_transient_descriptors_many_batches_in_flight(nt):
+    # 40 distinct batches (single- and multi-length, items in shuffled 2^16
+    # blocks, so every batch needs a descriptor) issued back to back on two
+    # streams with FLAG_TRANSIENT, more uploads in flight per stream than the
+    # staging ring has slots; each output equals the cached-descriptor form
+    S, BLK = 1 << 20, 1 << 16
+    rng = np.random.default_rng(31)
+    f = dev(rng.integers(0, M, S, dtype=np.uint32))
+    g = dev(rng.integers(0, M, S, dtype=np.uint32))
+    batches = []
+    for b in range(40):
+        k = int(rng.integers(2, 12))
+        blocks = rng.permutation(S // BLK)[:k]
+        if b % 3 == 0:
+            lens = [int(rng.integers(4, 17))] * k
+        else:
+            lens = [int(v) for v in rng.integers(4, 17, k)]
+        batches.append(nt.BatchDesc(lens, [int(x) * BLK for x in blocks]))
+    refs = []
+    for d in batches:
+        refs.append(host(nt.conv_batched(f, g, d, M)))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.zeros_like(f) for _ in batches]
+    torch.cuda.synchronize()
+    for i, d in enumerate(batches):
+        s = streams[i % 2]
+        with torch.cuda.stream(s):
+            nt.conv_batched(f, g, d, M, out=outs[i], flags=nt.FLAG_TRANSIENT, stream=s)
+    torch.cuda.synchronize()
+    for i, d in enumerate(batches):
+        o = host(outs[i])
+        for n, off in zip(d.log2n, d.offset):
+            a, z = int(off), int(off) + (1 << int(n))
+            assert np.array_equal(o[a:z], refs[i][a:z]), (i, int(n), a)
