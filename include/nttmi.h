@@ -135,9 +135,10 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
  * tuned with NTT_FLAG_AUTOTUNE for the batch's shape replaces the default.
  * Every form gives the same result.  Once the call has run on a stream (its
  * plans, workspaces and any tuning in place) it is capturable into a HIP graph
- * on that stream; the captured kernels keep the workspaces of that stream, so
- * a later call on the stream that needs a larger workspace (which frees the
- * old one) or ntt_release_caches invalidates the graph. */
+ * on that stream.  The captured kernels keep that stream's workspace and work
+ * queue: replay the graph on that stream, or ordered with every other use of
+ * it.  A workspace that a later call outgrows is retired, not freed, so the
+ * graph stays valid until ntt_release_caches. */
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc *d, const void *f, const void *g, void *h,
                         uint32_t flags, void *stream);

@@ -30,6 +30,7 @@ struct Plan {
 struct Buf {
     void* ptr = nullptr;
     size_t bytes = 0;
+    bool keep = false;   // descriptor cache: referenced by a captured graph, never evicted
 };
 
 // How conv_batched runs a batch: one persistent launch for the lengths it
@@ -47,21 +48,25 @@ struct BatchForm {
 };
 
 // Staging ring of transient descriptors on one stream.  Slot k owns a pinned
-// host buffer and a device buffer; an upload waits for the slot's previous
-// host-to-device copy (its event), fills the host buffer and enqueues the copy
-// on the stream.  Kernels that read the device buffer run on the same stream,
-// so the slot's next copy is ordered after them.
+// host buffer and a device buffer.  Each upload first records, on the stream,
+// the release event of the slot handed out before it: that event completes once
+// everything enqueued so far, the kernels that read that slot included, has
+// run.  A slot is refilled only after its release event has completed, so
+// neither of its buffers is overwritten while a copy or a kernel may still use
+// it, whatever the order in which the runtime executes small copies.
 constexpr int RING_SLOTS = 8;
 struct RingSlot {
     void* dev = nullptr;
     void* host = nullptr;
     size_t cap = 0;
-    hipEvent_t ev = nullptr;
+    hipEvent_t rel = nullptr;
+    bool recorded = false;
 };
 struct Ring {
     std::mutex mu;   // serialises uploads on the stream (the cache lock is not held while waiting)
     RingSlot slot[RING_SLOTS];
     unsigned next = 0;
+    int last = -1;   // slot handed out by the previous upload
 };
 
 struct Caches {
@@ -74,6 +79,7 @@ struct Caches {
     std::map<std::vector<uint64_t>, struct BatchForm> forms;          // batch shape -> tuned form
     std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
     std::map<std::pair<int, void*>, struct Ring> rings;               // (dev, stream) -> transient uploads
+    std::vector<void*> retired;                                       // outgrown workspaces
     std::map<uint64_t, std::pair<int, int>> moduli;                   // m -> (log2 nu or -1, v2(m-1) or -1)
     std::map<int, int> cu_count;                                      // dev -> CUs
 };
@@ -255,36 +261,43 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
 ntt_status get_buf(std::map<std::pair<int, void*>, Buf>& pool, void* stream, size_t bytes, void** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
-    std::lock_guard<std::mutex> g(caches().mu);
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
     Buf& b = pool[std::make_pair(dev, stream)];
     if (b.bytes < bytes) {
-        if (b.ptr) {
-            (void)hipStreamSynchronize((hipStream_t)stream);
-            (void)hipFree(b.ptr);
-            b.ptr = nullptr;
-            b.bytes = 0;
-        }
-        hipError_t e = hipMalloc(&b.ptr, bytes);
-        if (e != hipSuccess) {
-            b.ptr = nullptr;
-            return hip_status(e);
-        }
-        b.bytes = bytes;
+        // at least double, so that the retired buffers sum to less than the
+        // live one
+        const size_t cap = std::max(bytes, 2 * b.bytes);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, cap);
+        if (e != hipSuccess) return hip_status(e);
+        // the old buffer is retired, not freed: work enqueued earlier and
+        // graphs captured earlier keep using it (freed by ntt_release_caches)
+        if (b.ptr) c.retired.push_back(b.ptr);
+        b.ptr = p;
+        b.bytes = cap;
     }
     *out = b.ptr;
     return NTT_OK;
 }
 
 // Per-(device, stream) work queue of the persistent kernels: two uint32 words,
-// zeroed once here; every launch leaves them zero again.
+// zeroed once here, on the stream itself so that the first kernel is ordered
+// after the zeroing (a plain hipMemset runs on the null stream, which does not
+// order the non-blocking streams callers use); every launch leaves them zero
+// again.  Creation is refused while the stream is being captured (a call on
+// the stream before the capture creates the queue).
 ntt_status get_queue(void* stream, uint32_t** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
     std::lock_guard<std::mutex> g(caches().mu);
     Buf& b = caches().queue[std::make_pair(dev, stream)];
     if (!b.ptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return NTT_E_DEVICE;
         hipError_t e = hipMalloc(&b.ptr, 256);
-        if (e == hipSuccess) e = hipMemset(b.ptr, 0, 256);
+        if (e == hipSuccess) e = hipMemsetAsync(b.ptr, 0, 256, (hipStream_t)stream);
         if (e != hipSuccess) {
             if (b.ptr) (void)hipFree(b.ptr);
             b.ptr = nullptr;
@@ -297,7 +310,7 @@ ntt_status get_queue(void* stream, uint32_t** out) {
 }
 
 // Device copy of an offsets array, cached by content (uploaded once).
-ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out) {
+ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, bool keep = false) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
     Caches& c = caches();
@@ -306,9 +319,16 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out) {
     auto it = c.offsets.find(key);
     if (it == c.offsets.end()) {
         if (c.offsets.size() >= 256) {
+            // evict what no captured graph references, after the device is idle
             (void)hipDeviceSynchronize();
-            for (auto& kv : c.offsets) (void)hipFree(kv.second.ptr);
-            c.offsets.clear();
+            for (auto e = c.offsets.begin(); e != c.offsets.end();) {
+                if (e->second.keep) {
+                    ++e;
+                } else {
+                    (void)hipFree(e->second.ptr);
+                    e = c.offsets.erase(e);
+                }
+            }
         }
         Buf b;
         hipError_t e = hipMalloc(&b.ptr, h.size() * sizeof(uint64_t));
@@ -320,20 +340,26 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out) {
         b.bytes = h.size() * sizeof(uint64_t);
         it = c.offsets.emplace(key, b).first;
     }
+    if (keep) it->second.keep = true;
     *out = (const uint64_t*)it->second.ptr;
     return NTT_OK;
 }
 
 // Device copy of a descriptor used by one call: through the stream's staging
 // ring when `transient` and the stream is not being captured, else through the
-// content-addressed cache above.
+// content-addressed cache above (entries looked up under capture are kept for
+// the life of the caches).
+ntt_status stream_capturing(void* stream, bool* capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return NTT_E_DEVICE;
+    *capturing = cs != hipStreamCaptureStatusNone;
+    return NTT_OK;
+}
+
 ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream, const uint64_t** out) {
-    if (transient) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return NTT_E_DEVICE;
-        transient = cs == hipStreamCaptureStatusNone;
-    }
-    if (!transient) return get_offsets(h, out);
+    bool capturing = false;
+    if (stream_capturing(stream, &capturing) != NTT_OK) return NTT_E_DEVICE;
+    if (!transient || capturing) return get_offsets(h, out, capturing);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
@@ -346,16 +372,23 @@ ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream
     }
     Ring& r = *rp;
     std::lock_guard<std::mutex> g(r.mu);
-    RingSlot& sl = r.slot[r.next++ % RING_SLOTS];
     hipError_t e = hipSuccess;
-    if (sl.ev) e = hipEventSynchronize(sl.ev);          // the slot's previous copy has run
-    else e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    if (r.last >= 0) {
+        // the previous upload's kernels are enqueued by now
+        RingSlot& prev = r.slot[r.last];
+        e = hipEventRecord(prev.rel, s);
+        if (e != hipSuccess) return hip_status(e);
+        prev.recorded = true;
+    }
+    const int k = (int)(r.next++ % RING_SLOTS);
+    RingSlot& sl = r.slot[k];
+    if (!sl.rel) e = hipEventCreateWithFlags(&sl.rel, hipEventDisableTiming);
+    else if (sl.recorded) e = hipEventSynchronize(sl.rel);   // its last readers have run
     if (e != hipSuccess) return hip_status(e);
+    sl.recorded = false;
+    r.last = k;
     if (sl.cap < bytes) {
         if (sl.dev) {
-            // kernels enqueued earlier on this stream may still read the old buffer
-            e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_status(e);
             (void)hipFree(sl.dev);
             (void)hipHostFree(sl.host);
             sl.dev = sl.host = nullptr;
@@ -373,7 +406,6 @@ ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream
     }
     std::memcpy(sl.host, h.data(), h.size() * sizeof(uint64_t));
     e = hipMemcpyAsync(sl.dev, sl.host, h.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(sl.ev, s);
     if (e != hipSuccess) return hip_status(e);
     *out = (const uint64_t*)sl.dev;
     return NTT_OK;
@@ -557,8 +589,10 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
     std::memcpy(pw.data(), hp.data(), pw.size() * 8);
     const uint64_t* dblob = nullptr;
     const uint64_t* dplans = nullptr;
-    ntt_status st = NTT_OK;
-    if (transient) {
+    bool capturing = false;
+    ntt_status st = stream_capturing(stream, &capturing);
+    if (st != NTT_OK) return st;
+    if (transient && !capturing) {
         // one upload: items and tasks, padded to 16 bytes, then the plans
         const size_t plans_at = (blob.size() + 1) & ~(size_t)1;
         blob.resize(plans_at, 0);
@@ -567,9 +601,9 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
         if (st != NTT_OK) return st;
         dplans = dblob + plans_at;
     } else {
-        st = get_offsets(blob, &dblob);
+        st = get_desc(blob, false, stream, &dblob);
         if (st != NTT_OK) return st;
-        st = get_offsets(pw, &dplans);
+        st = get_desc(pw, false, stream, &dplans);
         if (st != NTT_OK) return st;
     }
     const size_t wb = elem_bits / 8;
@@ -1064,9 +1098,11 @@ void ntt_release_caches(void) {
         for (RingSlot& sl : kv.second.slot) {
             if (sl.dev) (void)hipFree(sl.dev);
             if (sl.host) (void)hipHostFree(sl.host);
-            if (sl.ev) (void)hipEventDestroy(sl.ev);
+            if (sl.rel) (void)hipEventDestroy(sl.rel);
         }
     c.rings.clear();
+    for (void* p : c.retired) (void)hipFree(p);
+    c.retired.clear();
 }
 
 }  // extern "C"

@@ -210,8 +210,45 @@ def test_transient_descriptors_many_batches_in_flight(nt):
         with torch.cuda.stream(s):
             nt.conv_batched(f, g, d, M, out=outs[i], flags=nt.FLAG_TRANSIENT, stream=s)
     torch.cuda.synchronize()
+    fh, gh = host(f), host(g)
     for i, d in enumerate(batches):
         o = host(outs[i])
         for n, off in zip(d.log2n, d.offset):
             a, z = int(off), int(off) + (1 << int(n))
-            assert np.array_equal(o[a:z], refs[i][a:z]), (i, int(n), a)
+            if not np.array_equal(o[a:z], refs[i][a:z]):
+                idx = np.array([0, (z - a) // 2, z - a - 1])
+                orc = oracle.conv_entries(fh[a:z], gh[a:z], M, idx).astype(np.uint32)
+                pytest.fail("batch %d item 2^%d at %d: transient zero=%s, transient==oracle %s, cached==oracle %s"
+                            % (i, int(n), a, bool((o[a:z] == 0).all()), bool(np.array_equal(o[a:z][idx], orc)),
+                               bool(np.array_equal(refs[i][a:z][idx], orc))))
+
+
+def test_first_call_on_fresh_streams_after_release(nt):
+    # regression: a stream's work queue is created (zeroed) at its first call;
+    # the zeroing must be ordered before that call's persistent kernel on the
+    # caller's non-blocking stream, also while another stream keeps the GPU busy
+    lengths = [14, 6, 15, 7, 5, 12, 16, 9]
+    offs = [int(i) << 16 for i in range(len(lengths))]
+    rng = np.random.default_rng(41)
+    S = len(lengths) << 16
+    f = dev(rng.integers(0, M, S, dtype=np.uint32))
+    g = dev(rng.integers(0, M, S, dtype=np.uint32))
+    desc = nt.BatchDesc(lengths, offs)
+    ref = host(nt.conv_batched(f, g, desc, M))
+    busy_n = 64 << 16
+    busy = dev(rng.integers(0, M, busy_n, dtype=np.uint32))
+    busy_desc = nt.BatchDesc([16] * 64, si.offsets([16] * 64))
+    for rep in range(3):
+        nt.release_caches()
+        a, b = torch.cuda.Stream(), torch.cuda.Stream()
+        out = torch.zeros_like(f)
+        busy_out = torch.zeros_like(busy)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(a):
+            nt.conv_batched(busy, busy, busy_desc, M, out=busy_out, stream=a)
+        with torch.cuda.stream(b):
+            nt.conv_batched(f, g, desc, M, out=out, stream=b)
+        torch.cuda.synchronize()
+        o = host(out)
+        for n, off in zip(lengths, offs):
+            assert np.array_equal(o[off:off + (1 << n)], ref[off:off + (1 << n)]), (rep, n)

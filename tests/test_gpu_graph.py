@@ -68,3 +68,42 @@ def test_graph_replay_matches_eager(nt, kind):
         graph.replay()
         torch.cuda.synchronize()
         assert np.array_equal(host(h), ref2), rep
+
+
+def test_graph_survives_workspace_growth_and_descriptor_churn(nt):
+    # after capture, eager calls on the same stream outgrow the workspace and
+    # push more than the descriptor cache's 256 entries through it; the graph's
+    # workspace is retired (not freed) and its descriptors are kept, so the
+    # replay still reads live memory and reproduces the eager result
+    lengths = tuple(si.uneven_batch(count=30, seed=9).log2n)
+    offs = si.offsets(lengths)
+    w = si.Workload("graph3", M, lengths, 32, M, 23)
+    f_h, g_h = si.operands(w)
+    f, g = dev(f_h), dev(g_h)
+    desc = nt.BatchDesc(lengths, offs)
+    ref = host(nt.conv_batched(f, g, desc, M))
+    stream = torch.cuda.Stream()
+    h = torch.zeros_like(f)
+    graph = _capture(nt, f, g, desc, h, stream)
+    torch.cuda.synchronize()
+
+    # a larger workspace on the capture stream: 64 items of 2^19 (64 resident
+    # workgroups of 4 MB scratch each, above the 30-item batch's)
+    big = torch.zeros(64 << 19, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(stream):
+        nt.conv_batched(big, big, nt.BatchDesc([19] * 64, si.offsets([19] * 64)), M, out=big.clone(),
+                        stream=stream)
+    # 300 distinct two-length descriptors through the cache
+    small = torch.zeros(1 << 15, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(stream):
+        for i in range(300):
+            nt.conv_batched(small, small, nt.BatchDesc([5, 6], [0, 64 + 64 * i]), M, out=small.clone(),
+                            stream=stream)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        h.fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(h), ref), rep
