@@ -176,7 +176,10 @@ hipError_t upload(T** d, const std::vector<T>& h) {
         *d = nullptr;
         return e;
     }
-    return hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    // complete before any stream may read it (the copy runs on the null stream)
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    return e;
 }
 
 // Device tables of the plan (m, N = 2^log2n, root): the powers root^e mod m,
@@ -333,6 +336,7 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, boo
         Buf b;
         hipError_t e = hipMalloc(&b.ptr, h.size() * sizeof(uint64_t));
         if (e == hipSuccess) e = hipMemcpy(b.ptr, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);   // complete before any stream reads it
         if (e != hipSuccess) {
             if (b.ptr) (void)hipFree(b.ptr);
             return hip_status(e);
