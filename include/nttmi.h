@@ -217,7 +217,9 @@ ntt_status ntt_copy_batch(void *const *dst, const void *const *src, const uint64
 /* Static description of a status code. */
 const char *ntt_status_string(ntt_status s);
 
-/* Frees every cached plan and workspace (waits for the device first). */
+/* Frees every cached plan, workspace, descriptor and staging slot (waits for
+ * the device first).  No other call of this library may run concurrently, and
+ * graphs captured before it must not be replayed after it. */
 void ntt_release_caches(void);
 
 #ifdef __cplusplus
