@@ -812,23 +812,24 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
     const char* F = (const char*)f;
     const char* Hh = (const char*)h;
     char* Gg = (char*)g;
-    const uint64_t N = 1ull << log2n;
     if ((int)log2n <= SMALL_MAX_LOG2N) {
         e = launch_conv_small((int)elem_bits, log2n, F, Hh, Gg, nullptr, batch, p->dev, s, SMALL_TILE_256,
                               (uint32_t*)flag);
     } else {
-        // rows in chunks whose scratch (2N words each) stays within 1 GiB
-        const uint64_t per = ((uint64_t)2 * wb) << log2n;
-        const uint32_t chunk = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (1ull << 30) / per), 65535);
+        // the persistent fused kernel with the quotient as its pointwise step:
+        // resident workgroups, each with 2N scratch words, within 1 GiB
+        const uint64_t per_wg = ((uint64_t)2 * wb) << log2n;
+        uint64_t grid = (uint64_t)std::max(1, cu_count()) * std::max(1, fused_blocks_per_cu((int)elem_bits, log2n, 1));
+        grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));
+        grid = std::min<uint64_t>(grid, batch);
         void* ws = nullptr;
-        st = get_buf(caches().work, stream, (size_t)(std::min<uint32_t>(chunk, batch) * per), &ws);
+        st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
         if (st != NTT_OK) return st;
-        for (uint32_t r = 0; r < batch && e == hipSuccess; r += chunk) {
-            const uint32_t k = std::min(chunk, batch - r);
-            const size_t o = (size_t)r * N * wb;
-            e = launch_conv_fourstep((int)elem_bits, log2n, F + o, Hh + o, Gg + o, k, N, ws, p->dev, s,
-                                     (uint32_t*)flag);
-        }
+        uint32_t* q = nullptr;
+        st = get_queue(stream, &q);
+        if (st != NTT_OK) return st;
+        e = launch_conv_fused((int)elem_bits, (int)log2n, F, Hh, Gg, nullptr, batch, ws, q, (uint32_t)grid, p->dev, s,
+                              (uint32_t*)flag);
     }
     uint32_t hflag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);

@@ -58,6 +58,52 @@ __device__ __forceinline__ double spectral(double F, double G, const DevPlan& p,
     }
 }
 
+template <class W, class FT>
+__device__ __forceinline__ double spec_in(FT x) {
+    if constexpr (std::is_same<FT, double>::value) return x;
+    else return W::from_s(x);
+}
+
+// The pointwise step over the E values of a work item: v[i] <- spectral(F[i],
+// v[i]).  OP_DIV inverts the E divisor values together (Montgomery's
+// simultaneous inversion): one Fermat power of the product of all E, then each
+// inverse from the prefix products while the running inverse is peeled back
+// factor by factor; 3 (E - 1) products and one power in place of E powers.  A
+// zero divisor value sets *singular and enters the products as 1.
+template <class W, int OP, int E, class FT>
+__device__ __forceinline__ void spectral_block(const FT* F, double* v, const DevPlan& p, const ModC& M,
+                                               uint32_t* singular) {
+    if constexpr (OP == OP_MUL || E == 1) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = spectral<W, OP>(spec_in<W>(F[i]), v[i], p, M, singular);
+    } else {
+        const double2 ni = make_double2(p.ninv, p.ninvq);
+        double c[E];   // c[i] = r_0 r_1 ... r_i
+        bool zero = false;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            double r = W::reduce_s(spec_in<W>(F[i]), M);
+            zero |= (r == 0.0);
+            r = (r == 0.0) ? 1.0 : r;
+            c[i] = (i == 0) ? r : W::mul_var(c[i - 1], r, M);
+        }
+        if (zero) atomicOr(singular, 1u);
+        const uint64_t e = (uint64_t)M.m - 2;
+        const int top = 63 - __builtin_clzll(e);
+        double inv = pow_mod<W>(c[E - 1], e, top, M);   // (r_0 ... r_{E-1})^-1
+#pragma unroll
+        for (int i = E - 1; i >= 1; --i) {
+            // r_i is formed again rather than kept (registers)
+            double r = W::reduce_s(spec_in<W>(F[i]), M);
+            r = (r == 0.0) ? 1.0 : r;
+            const double ri = W::mul_var(inv, c[i - 1], M);   // r_i^-1
+            inv = W::mul_var(inv, r, M);                       // (r_0 ... r_{i-1})^-1
+            v[i] = W::mul_var(ri, W::mul_tw(v[i], ni, M), M);
+        }
+        v[0] = W::mul_var(inv, W::mul_tw(v[0], ni, M), M);
+    }
+}
+
 // One tile of S convolutions of length L <= 2^12, entirely in the LDS of one
 // workgroup of S * max(1, L/16) threads: forward(f), forward(g), the product
 // with N^-1 folded in, inverse and the canonical store.  Item s of the tile
@@ -89,8 +135,12 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(g[off + B::pos0(j, i)], M);
     block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
     // pointwise step with N^-1 folded in
+    if constexpr (OP == OP_MUL) {
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = spectral<W, OP>(W::from_s(F[i]), v[i], p, M, singular);
+        for (int i = 0; i < B::E; ++i) v[i] = spectral<W, OP_MUL>(W::from_s(F[i]), v[i], p, M, singular);
+    } else {
+        spectral_block<W, OP, B::E>(F, v, p, M, singular);
+    }
     if (B::R0 != B::RL) {
         // output positions of the forward transform differ from the input
         // positions of the inverse: reorder through LDS
@@ -475,8 +525,12 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
         block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
                                                       twtab<W, G::A>(L.rowf, M));
     }
+    if constexpr (OP == OP_MUL) {   // (kept inline: the product path's register allocation)
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = spectral<W, OP>(F[i], v[i], p, M, singular);
+        for (int i = 0; i < B::E; ++i) v[i] = spectral<W, OP_MUL>(F[i], v[i], p, M, singular);
+    } else {
+        spectral_block<W, OP, B::E>(F, v, p, M, singular);
+    }
     if (B::R0 != B::RL) {
 #pragma unroll
         for (int i = 0; i < B::E; ++i) L.xch[B::lds(s, B::posL(j, i))] = v[i];
@@ -638,9 +692,10 @@ __global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* 
 // register (<= 128 VGPRs) budgets allow, two workgroups share a CU and hide
 // each other's memory and barrier latency; otherwise one workgroup per CU
 // issues the next block's loads before transforming the current block.
-template <class W, int LOGN>
+template <class W, int LOGN, int OP = OP_MUL>
 struct FusedCfg {
-    static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16;
+    // (the deconvolution's simultaneous inversion needs more registers)
+    static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16 && OP == OP_MUL;
     // minimum waves per SIMD (the second __launch_bounds__ argument): four
     // for two 512-thread workgroups per CU, i.e. at most 128 VGPRs
     static constexpr int WAVES_PER_EU = TWO ? 4 : 2;
@@ -671,17 +726,18 @@ __device__ __forceinline__ void queue_leave(uint32_t* q) {
 // rows (forward f, forward g, product with N^-1, inverse) back into Yf, then
 // the inverse columns into h.  With PREFETCH each block's loads are issued
 // before the previous block is transformed.  Ends with a barrier.
-template <class W, int LOGN, bool PREFETCH>
+template <class W, int LOGN, bool PREFETCH, int OP = OP_MUL>
 __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, const typename W::word* gi,
                                                 typename W::word* hi, typename W::sword* Yf,
-                                                typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN>& L) {
+                                                typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN>& L,
+                                                uint32_t* singular = nullptr) {
     using G = FS<LOGN>;
     constexpr int CL = G::A - G::SC;
     if constexpr (!PREFETCH) {
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(fi, Yf, c0, p, L);
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(gi, Yg, c0, p, L);
         __syncthreads();
-        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN, OP_MUL, false>(Yf, Yg, r0, p, L);
+        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN, OP, false>(Yf, Yg, r0, p, L, singular);
         __syncthreads();
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_inv_block<W, LOGN, false>(Yf, hi, c0, p, L);
         __syncthreads();
@@ -707,10 +763,10 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
         RowIn<W, LOGN> rin = row_conv_load<W, LOGN>(Yf, Yg, 0);
         for (int r0 = 0; r0 < G::Bn - G::SR; r0 += G::SR) {
             const RowIn<W, LOGN> nxt = row_conv_load<W, LOGN>(Yf, Yg, r0 + G::SR);
-            row_conv_compute<W, LOGN>(rin, Yf, r0, p, L);
+            row_conv_compute<W, LOGN, OP>(rin, Yf, r0, p, L, singular);
             rin = nxt;
         }
-        row_conv_compute<W, LOGN>(rin, Yf, G::Bn - G::SR, p, L);
+        row_conv_compute<W, LOGN, OP>(rin, Yf, G::Bn - G::SR, p, L, singular);
         __syncthreads();
         ColInvIn<W, LOGN> iin = col_inv_load<W, LOGN>(Yf, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
@@ -727,10 +783,10 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
 // one convolution at a time, start to finish, with a private 2N-word scratch,
 // and takes its next convolution from the work queue (workgroups that share a
 // CU do not progress at the same rate).
-template <class W, int LOGN>
-__global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::WAVES_PER_EU)) void k_conv_fused(
+template <class W, int LOGN, int OP = OP_MUL>
+__global__ __launch_bounds__(512, (FusedCfg<W, LOGN, OP>::WAVES_PER_EU)) void k_conv_fused(
     const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
-    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p) {
+    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p, uint32_t* singular) {
     using G = FS<LOGN>;
     __shared__ double lds[FSLds<LOGN>::WORDS];
     __shared__ uint32_t ticket;
@@ -741,7 +797,8 @@ __global__ __launch_bounds__(512, (FusedCfg<W, LOGN>::WAVES_PER_EU)) void k_conv
         const uint32_t item = queue_take(queue, &ticket);
         if (item >= count) break;
         const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
-        fused_conv_item<W, LOGN, !FusedCfg<W, LOGN>::TWO>(f + off, g + off, h + off, Yf, Yg, p, L);
+        fused_conv_item<W, LOGN, !FusedCfg<W, LOGN, OP>::TWO, OP>(f + off, g + off, h + off, Yf, Yg, p, L,
+                                                                 singular);
     }
     queue_leave(queue);
 }

@@ -49,11 +49,12 @@ hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, voi
                                const DevPlan& p, hipStream_t st);
 // scratch: grid * 2N scratch words; queue: two uint32 work-queue words, zero
 // before the launch and zero again after it (launches sharing a queue must be
-// ordered, e.g. on one stream)
+// ordered, e.g. on one stream).  singular != null selects the deconvolution
+// (h = g / f in the spectrum; a zero coefficient of f sets *singular).
 hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
                              uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
-                             hipStream_t st);
-int fused_blocks_per_cu(int wbits, int logn);
+                             hipStream_t st, uint32_t* singular = nullptr);
+int fused_blocks_per_cu(int wbits, int logn, int div = 0);
 // One launch for a batch of uneven lengths <= 2^multi_max_log2n(wbits).  tasks:
 // device array of {uint64 first item; uint32 log2n; uint32 item count} listed
 // longest first; toffs: device item offsets in task order; plans: device array

@@ -105,3 +105,20 @@ def test_deconv_detects_one_zero_bin(nt):
     with pytest.raises(nt.NttError) as e:
         nt.deconvolve(dev(f), dev(_draw(1, N, M)), M)
     assert e.value.name == "NTT_E_SINGULAR"
+
+
+def test_deconv_many_rows_through_the_work_queue(nt):
+    # more rows than resident workgroups: the persistent kernel's queue hands
+    # them out; every row recovers its g.  Random divisors of this length are
+    # singular with probability about N/m per row, so each divisor is made as
+    # the inverse transform of a spectrum drawn from [1, m): invertible.
+    n, rows = 14, 700
+    N = 1 << n
+    spec = np.random.default_rng(1700).integers(1, M, (rows, N), dtype=np.uint32)
+    f = host(nt.ntt_inverse(dev(spec), M))
+    g0 = _draw(1701, (rows, N), M)
+    lens = [n] * rows
+    offs = [r * N for r in range(rows)]
+    h = nt.conv_batched(dev(f.reshape(-1)), dev(g0.reshape(-1)), nt.BatchDesc(lens, offs), M)
+    g = host(nt.deconvolve(dev(f), h.reshape(rows, N), M))
+    assert np.array_equal(g, g0)
