@@ -214,6 +214,52 @@ ntt_status ntt_euler_root(uint64_t m, uint32_t log2n, uint64_t *root);
 ntt_status ntt_copy_batch(void *const *dst, const void *const *src, const uint64_t *bytes, uint32_t count,
                           void *stream);
 
+/* Native served form (plumbing around conv_batched, no arithmetic of its own):
+ * a server owns three device arenas of 2^arena_log2 words (f, g, h), a set of
+ * non-blocking streams and one scheduler thread.  ntt_server_submit copies a
+ * request's operands (host memory) into a pinned staging block and queues it;
+ * the scheduler admits queued requests in arrival order while a buddy
+ * allocator over the arenas has room (every request takes one slot of its
+ * length, the same offset in all three arenas), at most max_batch requests
+ * and max_batch_elems arena words per batch (one larger request still goes
+ * alone), with at most max_inflight batches on the device; a batch is one
+ * upload call, one conv_batched call (NTT_FLAG_TRANSIENT) and one download on
+ * the next stream.  ntt_server_wait blocks until the request is done and copies
+ * its result to host memory.  Requests use root^(2^(root_log2order - log2n)),
+ * as in conv_batched. */
+typedef struct ntt_server ntt_server;
+
+/* Creates a server.  elem_bits, m, root and root_log2order as for conv_batched;
+ * arena_log2 <= 28; streams in [1, 16]; max_batch >= 1; max_batch_elems 0 means
+ * the whole arena; max_inflight >= 1.  Allocates the arenas on the current
+ * device.  NTT_E_ARG, NTT_E_MODULUS, NTT_E_LENGTH, NTT_E_ROOT as for
+ * conv_batched; NTT_E_NOMEM; NTT_E_DEVICE. */
+ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
+                             uint32_t arena_log2, uint32_t streams, uint32_t max_batch, uint64_t max_batch_elems,
+                             uint32_t max_inflight, ntt_server **out);
+
+/* Queues the convolution of f and g (host arrays of 2^log2n words each, read
+ * before the call returns) and writes its ticket.  NTT_E_LENGTH: log2n above
+ * root_log2order or arena_log2; NTT_E_ARG: null pointer or a stopped server;
+ * NTT_E_NOMEM: no pinned staging memory. */
+ntt_status ntt_server_submit(ntt_server *srv, const void *f, const void *g, uint32_t log2n, uint64_t *ticket);
+
+/* Waits up to timeout_s seconds (negative: no limit) for the request, copies
+ * its 2^log2n result words to h (host) and releases the ticket.  NTT_E_ARG: an
+ * unknown ticket; NTT_E_DEVICE: its batch failed (the ticket is released);
+ * NTT_E_UNSUPPORTED: the time ran out (the ticket stays valid). */
+ntt_status ntt_server_wait(ntt_server *srv, uint64_t ticket, void *h, double timeout_s);
+
+/* Completed requests since creation or the last reset, the mean requests per
+ * batch, and the p50 / p99 of submit-to-completion latency in milliseconds
+ * (completion as the scheduler observes it).  reset != 0 clears them. */
+ntt_status ntt_server_stats(ntt_server *srv, uint64_t *completed, double *mean_batch, double *p50_ms,
+                            double *p99_ms, uint32_t reset);
+
+/* Finishes every queued and running request, stops the thread and frees the
+ * server.  Tickets not yet waited for are released. */
+void ntt_server_destroy(ntt_server *srv);
+
 /* Static description of a status code. */
 const char *ntt_status_string(ntt_status s);
 

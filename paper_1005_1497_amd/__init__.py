@@ -93,6 +93,18 @@ def _load():
     L.ntt_euler_root.restype = I32
     L.ntt_copy_batch.argtypes = [VP, VP, VP, U32, VP]
     L.ntt_copy_batch.restype = I32
+    D = ctypes.c_double
+    L.ntt_server_create.argtypes = [U64, U64, U32, U32, U32, U32, U32, U64, U32, ctypes.POINTER(VP)]
+    L.ntt_server_create.restype = I32
+    L.ntt_server_submit.argtypes = [VP, VP, VP, U32, ctypes.POINTER(U64)]
+    L.ntt_server_submit.restype = I32
+    L.ntt_server_wait.argtypes = [VP, U64, VP, D]
+    L.ntt_server_wait.restype = I32
+    L.ntt_server_stats.argtypes = [VP, ctypes.POINTER(U64), ctypes.POINTER(D), ctypes.POINTER(D),
+                                   ctypes.POINTER(D), U32]
+    L.ntt_server_stats.restype = I32
+    L.ntt_server_destroy.argtypes = [VP]
+    L.ntt_server_destroy.restype = None
     L.ntt_status_string.argtypes = [I32]
     L.ntt_status_string.restype = ctypes.c_char_p
     L.ntt_release_caches.argtypes = []

@@ -20,7 +20,7 @@ HIP_FLAGS = [
 
 def sources():
     names = sorted(f for f in os.listdir(CSRC) if f.startswith("launch_") and f.endswith(".hip"))
-    return [os.path.join(CSRC, f) for f in names] + [os.path.join(CSRC, "api.cpp")]
+    return [os.path.join(CSRC, f) for f in names] + [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "server.cpp")]
 
 
 def build(verbose: bool = False) -> str:

@@ -754,6 +754,37 @@ ntt_status autotune(const std::map<uint32_t, std::vector<uint64_t>>& cls, std::m
 
 }  // namespace
 
+namespace nttmi {
+
+// Drops the per-stream state of `stream` on the current device (workspace,
+// flag, work queue, tuning buffer, descriptor ring) once the stream is idle;
+// for owners of streams that are about to be destroyed.
+void release_stream_caches(void* stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
+    const auto key = std::make_pair(dev, stream);
+    for (auto* pool : {&c.work, &c.flag, &c.queue, &c.tune}) {
+        auto it = pool->find(key);
+        if (it == pool->end()) continue;
+        if (it->second.ptr) (void)hipFree(it->second.ptr);
+        pool->erase(it);
+    }
+    auto r = c.rings.find(key);
+    if (r != c.rings.end()) {
+        for (RingSlot& sl : r->second.slot) {
+            if (sl.dev) (void)hipFree(sl.dev);
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.rel) (void)hipEventDestroy(sl.rel);
+        }
+        c.rings.erase(r);
+    }
+}
+
+}  // namespace nttmi
+
 extern "C" {
 
 ntt_status ntt_forward(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* x, void* X,

@@ -392,3 +392,58 @@ class ConvServer:
                 with self._lock:
                     if not self._stop:
                         self._wake.wait(timeout=0.0002)
+
+
+class NativeConvServer:
+    """The served form run by the library's own scheduler thread (ntt_server_*
+    in the C ABI): the same admission, batching and stream rotation as
+    ConvServer, with no Python on the per-request path.  submit() copies f and
+    g into a pinned staging block inside the library (the interpreter lock is
+    released during the call) and returns a ticket; result() waits for it."""
+
+    def __init__(self, m: int, capacity_log2: int, elem_bits: int = 64, streams: int = 4, max_batch: int = 512,
+                 max_batch_elems: int = 0, max_inflight: int = 4, root: int = 2, root_log2order: int | None = None):
+        import ctypes
+        import paper_1005_1497_amd as nt
+        self._nt, self._ct = nt, ctypes
+        self.np_dtype = np.uint64 if elem_bits == 64 else np.uint32
+        rlo = root_log2order if root_log2order is not None else nt.modulus_order(m)
+        h = ctypes.c_void_p()
+        nt._check(nt.lib.ntt_server_create(m, root, rlo, elem_bits, capacity_log2, streams, max_batch,
+                                            max_batch_elems, max_inflight, ctypes.byref(h)), "ntt_server_create")
+        self._h = h
+
+    def submit(self, f: np.ndarray, g: np.ndarray) -> int:
+        f = np.ascontiguousarray(f, dtype=self.np_dtype)
+        g = np.ascontiguousarray(g, dtype=self.np_dtype)
+        n = f.size
+        if f.shape != g.shape or f.ndim != 1 or n == 0 or n & (n - 1):
+            raise ValueError("f and g must be 1-D of the same power-of-two length")
+        t = self._ct.c_uint64()
+        self._nt._check(self._nt.lib.ntt_server_submit(self._h, f.ctypes.data, g.ctypes.data, n.bit_length() - 1,
+                                                       self._ct.byref(t)), "ntt_server_submit")
+        return (t.value, n)
+
+    def result(self, ticket, timeout: float = -1.0) -> np.ndarray:
+        tid, n = ticket
+        out = np.empty(n, dtype=self.np_dtype)
+        self._nt._check(self._nt.lib.ntt_server_wait(self._h, tid, out.ctypes.data, timeout), "ntt_server_wait")
+        return out
+
+    def stats(self, reset: bool = False) -> dict:
+        ct = self._ct
+        c, mb, p50, p99 = ct.c_uint64(), ct.c_double(), ct.c_double(), ct.c_double()
+        self._nt._check(self._nt.lib.ntt_server_stats(self._h, ct.byref(c), ct.byref(mb), ct.byref(p50),
+                                                      ct.byref(p99), 1 if reset else 0), "ntt_server_stats")
+        return {"completed": c.value, "mean_batch": mb.value, "p50_ms": p50.value, "p99_ms": p99.value}
+
+    def close(self):
+        if self._h:
+            self._nt.lib.ntt_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -47,6 +47,16 @@ def lib():
     L.ntt_euler_root.restype = I32
     L.ntt_copy_batch.argtypes = [VP, VP, VP, U32, VP]
     L.ntt_copy_batch.restype = I32
+    L.ntt_server_create.argtypes = [U64, U64, U32, U32, U32, U32, U32, U64, U32, ctypes.POINTER(VP)]
+    L.ntt_server_create.restype = I32
+    L.ntt_server_submit.argtypes = [VP, VP, VP, U32, ctypes.POINTER(U64)]
+    L.ntt_server_submit.restype = I32
+    L.ntt_server_wait.argtypes = [VP, U64, VP, ctypes.c_double]
+    L.ntt_server_wait.restype = I32
+    L.ntt_server_stats.argtypes = [VP, VP, VP, VP, VP, U32]
+    L.ntt_server_stats.restype = I32
+    L.ntt_server_destroy.argtypes = [VP]
+    L.ntt_server_destroy.restype = None
     L.ntt_status_string.argtypes = [I32]
     L.ntt_status_string.restype = ctypes.c_char_p
     return L
@@ -198,3 +208,22 @@ def test_copy_batch_validation(lib):
     src = np.array([0x2000, 0x3000], np.uint64)
     nb = np.array([8, 8], np.uint64)                                      # entry 1 has a null dst
     assert lib.ntt_copy_batch(dst.ctypes.data, src.ctypes.data, nb.ctypes.data, 2, None) == 1
+
+
+def test_server_argument_validation(lib):
+    # host-side checks before any device work
+    h = ctypes.c_void_p()
+    M = 13631489
+    assert lib.ntt_server_create(M, 2, 19, 32, 20, 4, 512, 0, 4, None) == 1            # no out pointer
+    assert lib.ntt_server_create(M, 2, 19, 32, 29, 4, 512, 0, 4, ctypes.byref(h)) == 1  # arena too large
+    assert lib.ntt_server_create(M, 2, 19, 32, 20, 0, 512, 0, 4, ctypes.byref(h)) == 1  # no stream
+    assert lib.ntt_server_create(M, 2, 19, 32, 20, 17, 512, 0, 4, ctypes.byref(h)) == 1  # too many streams
+    assert lib.ntt_server_create(M, 2, 19, 32, 20, 4, 0, 0, 4, ctypes.byref(h)) == 1    # empty batches
+    assert lib.ntt_server_create(M, 2, 19, 32, 20, 4, 512, 0, 0, ctypes.byref(h)) == 1  # nothing in flight
+    assert lib.ntt_server_create(M + 2, 2, 19, 32, 20, 4, 512, 0, 4, ctypes.byref(h)) == 2  # not a valid modulus
+    assert lib.ntt_server_create(M, 3, 19, 32, 20, 4, 512, 0, 4, ctypes.byref(h)) == 4  # 3 has not order 2^19
+    t = ctypes.c_uint64()
+    assert lib.ntt_server_submit(None, None, None, 4, ctypes.byref(t)) == 1
+    assert lib.ntt_server_wait(None, 1, None, 0.0) == 1
+    assert lib.ntt_server_stats(None, None, None, None, None, 0) == 1
+    lib.ntt_server_destroy(None)

@@ -69,3 +69,58 @@ def test_zero_copy_submission_and_result_lifetime():
         assert np.array_equal(a, b)
     for (f, g), fu in zip(ops, futs):
         assert np.array_equal(fu.result(), host(nt.conv_circular(dev(f), dev(g), m)))
+
+
+@pytest.mark.parametrize("bits,m", [(64, si.M_U64), (32, si.M_13631489)])
+def test_native_server_equals_alone(bits, m):
+    # the library's own scheduler thread: every result equals the request run
+    # alone; two client threads submit at once; the oracle checks a few entries
+    import threading
+
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import NativeConvServer
+    rng = np.random.default_rng(11)
+    lens = si.served_lengths(200, seed=6) if bits == 64 else rng.integers(4, 16, 200)
+    dt = np.uint64 if bits == 64 else np.uint32
+    reqs = [(rng.integers(0, m, 1 << int(n), dtype=dt), rng.integers(0, m, 1 << int(n), dtype=dt)) for n in lens]
+    tickets = [None] * len(reqs)
+    with NativeConvServer(m, capacity_log2=21, elem_bits=bits, streams=4, max_batch_elems=1 << 19) as srv:
+        def client(part):
+            for i in range(part, len(reqs), 2):
+                tickets[i] = srv.submit(*reqs[i])
+
+        ths = [threading.Thread(target=client, args=(k,)) for k in range(2)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        outs = [srv.result(t, timeout=60.0) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs)
+    assert st["mean_batch"] > 1
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    for (f, g), o in zip(reqs, outs):
+        assert np.array_equal(o, host(nt.conv_circular(dev(f), dev(g), m)))
+    for k in (0, len(reqs) - 1):
+        f, g = reqs[k]
+        idx = np.array([0, f.size - 1])
+        assert np.array_equal(outs[k][idx], oracle.conv_entries(f, g, m, idx).astype(dt))
+
+
+def test_native_server_admission_and_shutdown():
+    # an arena of 2^14 words and requests of 2^12..2^14: admission waits for
+    # slots; tickets not waited for are released at shutdown
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import NativeConvServer
+    m = si.M_13631489
+    rng = np.random.default_rng(12)
+    reqs = [(rng.integers(0, m, 1 << int(n), dtype=np.uint32), rng.integers(0, m, 1 << int(n), dtype=np.uint32))
+            for n in rng.integers(12, 15, 40)]
+    srv = NativeConvServer(m, capacity_log2=14, elem_bits=32, streams=2, max_inflight=2)
+    tickets = [srv.submit(f, g) for f, g in reqs]
+    for (f, g), t in list(zip(reqs, tickets))[:30]:
+        assert np.array_equal(srv.result(t, timeout=60.0), host(nt.conv_circular(dev(f), dev(g), m)))
+    with pytest.raises(nt.NttError) as e:
+        srv.submit(np.zeros(1 << 15, np.uint32), np.zeros(1 << 15, np.uint32))    # larger than the arena
+    assert e.value.name == "NTT_E_LENGTH"
+    srv.close()                                   # ten tickets still pending
