@@ -441,10 +441,12 @@ def variant_bench(args):
 def serve_bench(args):
     """Serving: Poisson arrivals of convolution requests, lengths 2^n with n
     uniform in [8, 18], m = 31065037602817 (64-bit words), continuous batching
-    over four streams, at most a quarter of the arena per batch; p50/p99 latency and throughput at offered load
-    rho * (saturated throughput), with operands copied in at submission and
-    with zero-copy submission (operands already in pinned staging blocks),
-    against one launch sequence per request."""
+    over four streams, at most a quarter of the arena per batch; p50/p99
+    latency and throughput at offered load rho * (saturated throughput).  The
+    headline runs the library's native
+    scheduler (ntt_server_*); beside it, the same at one request per batch, and
+    the Python scheduler with operands copied in at submission and with
+    zero-copy submission, against one launch sequence per request."""
     import threading
 
     import paper_1005_1497_amd.serve as sv
@@ -516,11 +518,67 @@ def serve_bench(args):
                 "p99_ms": st.percentile(99) * 1e3, "mean_batch": float(np.mean(st.batch_sizes)),
                 "peak_inflight_batches": st.peak_inflight, "elapsed_s": el}
 
+    def run_native(rate, max_batch=512):
+        """The library's scheduler thread (ntt_server_*): a producer thread
+        submits with Poisson gaps (the copy into pinned staging runs inside the
+        library), a consumer thread collects the results in order into a reused
+        buffer; latency is measured inside the library from submission to
+        completion."""
+        srv = sv.NativeConvServer(m, capacity_log2=cap, elem_bits=64, streams=4, max_batch=max_batch,
+                                  max_batch_elems=1 << (cap - 2), max_inflight=4)
+        for t in [srv.submit(f, g) for f, g in reqs[:warm]]:
+            srv.result(t)
+        srv.stats(reset=True)
+        body = reqs[warm:]
+        gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
+        tickets = [None] * len(body)
+        ready = threading.Semaphore(0)
+        gc.collect()
+        gc.freeze()
+        t_start = time.perf_counter()
+
+        def producer():
+            nxt = time.perf_counter()
+            for i, ((f, g), gap) in enumerate(zip(body, gaps)):
+                nxt += gap
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(f, g)
+                ready.release()
+
+        sink = np.empty(1 << 18, dtype=np.uint64)     # the client's reused result buffer
+        sink.fill(0)                                   # (its pages faulted in before timing)
+
+        def consumer():
+            for i in range(len(body)):
+                ready.acquire()
+                srv.result(tickets[i], out=sink[:tickets[i][1]])
+
+        ths = [threading.Thread(target=producer), threading.Thread(target=consumer)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        el = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        return {"throughput_conv_per_s": len(body) / el, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "mean_batch": st["mean_batch"], "elapsed_s": el}
+
     sat = run(reqs, None, 512)
-    log("closed loop: %.0f conv/s" % sat["throughput_conv_per_s"])
+    log("python closed loop: %.0f conv/s" % sat["throughput_conv_per_s"])
     rate = args.rho * sat["throughput_conv_per_s"]
     served = run(reqs, rate, 512)
-    log("served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (rate, served["p50_ms"], served["p99_ms"]))
+    log("python served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (rate, served["p50_ms"], served["p99_ms"]))
+    nat_sat = run_native(None)
+    log("native closed loop: %.0f conv/s" % nat_sat["throughput_conv_per_s"])
+    nat_rate = args.rho * nat_sat["throughput_conv_per_s"]
+    nat = run_native(nat_rate)
+    log("native served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (nat_rate, nat["p50_ms"], nat["p99_ms"]))
+    nat_same = run_native(rate)
+    log("native served at %.0f/s: p50 %.3f ms p99 %.3f ms" % (rate, nat_same["p50_ms"], nat_same["p99_ms"]))
+    nat_single = run_native(rate, max_batch=1)
     zc_sat = run(reqs, None, 512, zero_copy=True)
     log("zero-copy closed loop: %.0f conv/s" % zc_sat["throughput_conv_per_s"])
     zc_rate = args.rho * zc_sat["throughput_conv_per_s"]
@@ -532,14 +590,16 @@ def serve_bench(args):
     single_at_rate = run(reqs, rate, 1) if rate <= single_sat["throughput_conv_per_s"] else None
     out = {
         "metric": "served exact convolutions: throughput and p50/p99 latency",
-        "value": served["throughput_conv_per_s"], "unit": "conv/s", "n_gpus": 1, "steps": n, "warmup": warm,
+        "value": nat["throughput_conv_per_s"], "unit": "conv/s", "n_gpus": 1, "steps": n, "warmup": warm,
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-        "latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"]},
-        "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "rho": args.rho, "offered_per_s": rate,
-                   "words": "u64", "streams": 4,
+        "latency_ms": {"p50": nat["p50_ms"], "p99": nat["p99_ms"]},
+        "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "rho": args.rho,
+                   "offered_per_s": nat_rate, "scheduler": "native (ntt_server_*)", "words": "u64", "streams": 4,
                    "max_batch_elems": 1 << (cap - 2)},
-        "saturated": sat, "served": served,
-        "forms": {"zero_copy_saturated": zc_sat, "zero_copy_at_rho": zc, "zero_copy_at_same_rate": zc_same,
+        "saturated": nat_sat, "served": nat,
+        "forms": {"native_at_python_rate": nat_same, "native_one_request_per_batch_at_python_rate": nat_single,
+                  "python_saturated": sat, "python_at_rho": served,
+                  "zero_copy_saturated": zc_sat, "zero_copy_at_rho": zc, "zero_copy_at_same_rate": zc_same,
                   "one_launch_per_request_saturated": single_sat, "one_launch_per_request_at_rho": single,
                   "one_launch_per_request_at_same_rate": single_at_rate},
     }

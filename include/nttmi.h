@@ -231,8 +231,9 @@ typedef struct ntt_server ntt_server;
 
 /* Creates a server.  elem_bits, m, root and root_log2order as for conv_batched;
  * arena_log2 <= 28; streams in [1, 16]; max_batch >= 1; max_batch_elems 0 means
- * the whole arena; max_inflight >= 1.  Allocates the arenas on the current
- * device.  NTT_E_ARG, NTT_E_MODULUS, NTT_E_LENGTH, NTT_E_ROOT as for
+ * the whole arena; max_inflight >= 1.  Allocates the arenas and, per stream,
+ * the scratch workspace the batch kernels may take (at most 1 GiB), on the
+ * current device.  NTT_E_ARG, NTT_E_MODULUS, NTT_E_LENGTH, NTT_E_ROOT as for
  * conv_batched; NTT_E_NOMEM; NTT_E_DEVICE. */
 ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                              uint32_t arena_log2, uint32_t streams, uint32_t max_batch, uint64_t max_batch_elems,
@@ -244,9 +245,20 @@ ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order,
  * NTT_E_NOMEM: no pinned staging memory. */
 ntt_status ntt_server_submit(ntt_server *srv, const void *f, const void *g, uint32_t log2n, uint64_t *ticket);
 
+/* Zero-copy submission, first half: reserves a staging block for a request of
+ * 2^log2n words without queueing it, and writes host pointers to its f and g
+ * rows (pinned memory owned by the server) and its ticket.  Fill both rows,
+ * then call ntt_server_submit_staged.  Errors as for ntt_server_submit. */
+ntt_status ntt_server_stage(ntt_server *srv, uint32_t log2n, void **f, void **g, uint64_t *ticket);
+
+/* Zero-copy submission, second half: queues a staged request (its arrival
+ * time is now).  NTT_E_ARG: an unknown ticket or one already queued. */
+ntt_status ntt_server_submit_staged(ntt_server *srv, uint64_t ticket);
+
 /* Waits up to timeout_s seconds (negative: no limit) for the request, copies
  * its 2^log2n result words to h (host) and releases the ticket.  NTT_E_ARG: an
- * unknown ticket; NTT_E_DEVICE: its batch failed (the ticket is released);
+ * unknown ticket or a staged one never queued; NTT_E_DEVICE: its batch failed
+ * (the ticket is released);
  * NTT_E_UNSUPPORTED: the time ran out (the ticket stays valid). */
 ntt_status ntt_server_wait(ntt_server *srv, uint64_t ticket, void *h, double timeout_s);
 

@@ -98,6 +98,10 @@ def _load():
     L.ntt_server_create.restype = I32
     L.ntt_server_submit.argtypes = [VP, VP, VP, U32, ctypes.POINTER(U64)]
     L.ntt_server_submit.restype = I32
+    L.ntt_server_stage.argtypes = [VP, U32, ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(U64)]
+    L.ntt_server_stage.restype = I32
+    L.ntt_server_submit_staged.argtypes = [VP, U64]
+    L.ntt_server_submit_staged.restype = I32
     L.ntt_server_wait.argtypes = [VP, U64, VP, D]
     L.ntt_server_wait.restype = I32
     L.ntt_server_stats.argtypes = [VP, ctypes.POINTER(U64), ctypes.POINTER(D), ctypes.POINTER(D),

@@ -79,7 +79,8 @@ struct Caches {
     std::map<std::vector<uint64_t>, struct BatchForm> forms;          // batch shape -> tuned form
     std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
     std::map<std::pair<int, void*>, struct Ring> rings;               // (dev, stream) -> transient uploads
-    std::vector<void*> retired;                                       // outgrown workspaces
+    std::vector<void*> retired;                                       // outgrown device buffers
+    std::vector<void*> retired_host;                                  // outgrown pinned staging
     std::map<uint64_t, std::pair<int, int>> moduli;                   // m -> (log2 nu or -1, v2(m-1) or -1)
     std::map<int, int> cu_count;                                      // dev -> CUs
 };
@@ -392,20 +393,23 @@ ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream
     sl.recorded = false;
     r.last = k;
     if (sl.cap < bytes) {
-        if (sl.dev) {
-            (void)hipFree(sl.dev);
-            (void)hipHostFree(sl.host);
-            sl.dev = sl.host = nullptr;
-            sl.cap = 0;
-        }
-        const size_t cap = std::max<size_t>(bytes, 4096);
-        e = hipMalloc(&sl.dev, cap);
-        if (e == hipSuccess) e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+        // at least double; the outgrown buffers are retired, not freed (a free
+        // would wait for the whole device)
+        const size_t cap = std::max<size_t>({bytes, 2 * sl.cap, 65536});
+        void *d = nullptr, *hh = nullptr;
+        e = hipMalloc(&d, cap);
+        if (e == hipSuccess) e = hipHostMalloc(&hh, cap, hipHostMallocDefault);
         if (e != hipSuccess) {
-            if (sl.dev) (void)hipFree(sl.dev);
-            sl.dev = sl.host = nullptr;
+            if (d) (void)hipFree(d);
             return hip_status(e);
         }
+        if (sl.dev || sl.host) {
+            std::lock_guard<std::mutex> gc(c.mu);
+            if (sl.dev) c.retired.push_back(sl.dev);
+            if (sl.host) c.retired_host.push_back(sl.host);
+        }
+        sl.dev = d;
+        sl.host = hh;
         sl.cap = cap;
     }
     std::memcpy(sl.host, h.data(), h.size() * sizeof(uint64_t));
@@ -755,6 +759,17 @@ ntt_status autotune(const std::map<uint32_t, std::vector<uint64_t>>& cls, std::m
 }  // namespace
 
 namespace nttmi {
+
+// Sizes the workspace of `stream` to at least `bytes` and creates its work
+// queue now, so that later calls on the stream allocate nothing (for owners
+// of long-lived streams, such as the native server).
+ntt_status reserve_stream(void* stream, size_t bytes) {
+    void* ws = nullptr;
+    ntt_status st = get_buf(caches().work, stream, bytes, &ws);
+    uint32_t* q = nullptr;
+    if (st == NTT_OK) st = get_queue(stream, &q);
+    return st;
+}
 
 // Drops the per-stream state of `stream` on the current device (workspace,
 // flag, work queue, tuning buffer, descriptor ring) once the stream is idle;
@@ -1139,6 +1154,8 @@ void ntt_release_caches(void) {
     c.rings.clear();
     for (void* p : c.retired) (void)hipFree(p);
     c.retired.clear();
+    for (void* p : c.retired_host) (void)hipHostFree(p);
+    c.retired_host.clear();
 }
 
 }  // extern "C"

@@ -25,7 +25,8 @@
 #include "../../include/nttmi.h"
 
 namespace nttmi {
-void release_stream_caches(void* stream);   // api.cpp
+ntt_status reserve_stream(void* stream, size_t bytes);   // api.cpp
+void release_stream_caches(void* stream);             // api.cpp
 }
 
 namespace {
@@ -98,7 +99,7 @@ class PinnedPool {
     std::vector<void*> all_;
 };
 
-enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2, Q_FAILED = 3 };
+enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2, Q_FAILED = 3, Q_STAGED = 4 };
 
 struct Req {
     uint64_t id = 0;
@@ -286,13 +287,24 @@ ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order,
     if (e == hipSuccess) e = hipMalloc((void**)&s->F, bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&s->G, bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&s->H, bytes);
+    // the largest scratch a batch launch takes: at most two resident
+    // workgroups per CU, 2N words each for N up to the arena, and never more
+    // than 1 GiB; reserved with each stream's work queue now rather than on
+    // the request path
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->dev);
+    const size_t reserve = std::min<size_t>(size_t(1) << 30, size_t(2) * (size_t)std::max(cus, 1) * bytes * 2);
     for (uint32_t i = 0; i < streams && e == hipSuccess; ++i) {
         hipStream_t h = nullptr;
         e = hipStreamCreateWithFlags(&h, hipStreamNonBlocking);
         if (e == hipSuccess) s->streams.push_back(h);
+        if (e == hipSuccess && nttmi::reserve_stream(h, reserve) != NTT_OK) e = hipErrorOutOfMemory;
     }
     if (e != hipSuccess) {
-        for (hipStream_t h : s->streams) (void)hipStreamDestroy(h);
+        for (hipStream_t h : s->streams) {
+            nttmi::release_stream_caches(h);
+            (void)hipStreamDestroy(h);
+        }
         if (s->F) (void)hipFree(s->F);
         if (s->G) (void)hipFree(s->G);
         if (s->H) (void)hipFree(s->H);
@@ -334,12 +346,53 @@ ntt_status ntt_server_submit(ntt_server* s, const void* f, const void* g, uint32
     return NTT_OK;
 }
 
+ntt_status ntt_server_stage(ntt_server* s, uint32_t log2n, void** f, void** g, uint64_t* ticket) {
+    if (!s || !f || !g || !ticket) return NTT_E_ARG;
+    if (log2n > s->rlo || log2n > s->arena_log2) return NTT_E_LENGTH;
+    const size_t row = (size_t(1) << log2n) * s->wb;
+    char* st = (char*)s->pool.get(3 * row);
+    if (!st) return NTT_E_NOMEM;
+    Req* r = new Req();
+    r->log2n = log2n;
+    r->staging = st;
+    r->staging_bytes = 3 * row;
+    r->state = Q_STAGED;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+        s->pool.put(st, 3 * row);
+        delete r;
+        return NTT_E_ARG;
+    }
+    r->id = s->next_id++;
+    s->reqs[r->id] = r;
+    *ticket = r->id;
+    *f = st;
+    *g = st + row;
+    return NTT_OK;
+}
+
+ntt_status ntt_server_submit_staged(ntt_server* s, uint64_t ticket) {
+    if (!s) return NTT_E_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end() || it->second->state != Q_STAGED || s->stop) return NTT_E_ARG;
+        Req* r = it->second;
+        r->arrival = Clock::now();
+        r->state = Q_QUEUED;
+        s->queue.push_back(r);
+    }
+    s->cv_sched.notify_one();
+    return NTT_OK;
+}
+
 ntt_status ntt_server_wait(ntt_server* s, uint64_t ticket, void* h, double timeout_s) {
     if (!s || !h) return NTT_E_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return NTT_E_ARG;
     Req* r = it->second;
+    if (r->state == Q_STAGED) return NTT_E_ARG;   // never queued
     auto ready = [r] { return r->state == Q_DONE || r->state == Q_FAILED; };
     if (timeout_s < 0) {
         s->cv_done.wait(lk, ready);

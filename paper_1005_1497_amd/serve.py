@@ -424,9 +424,33 @@ class NativeConvServer:
                                                        self._ct.byref(t)), "ntt_server_submit")
         return (t.value, n)
 
-    def result(self, ticket, timeout: float = -1.0) -> np.ndarray:
+    def stage(self, n: int):
+        """Zero-copy submission, first half: (f, g, ticket) with f and g
+        writable arrays over the pinned rows of a staging block inside the
+        library.  Fill them, then call submit_staged(ticket); they are not to
+        be touched after result()."""
+        if n <= 0 or n & (n - 1):
+            raise ValueError("request length must be a power of two")
+        ct = self._ct
+        fp, gp, t = ct.c_void_p(), ct.c_void_p(), ct.c_uint64()
+        self._nt._check(self._nt.lib.ntt_server_stage(self._h, n.bit_length() - 1, ct.byref(fp), ct.byref(gp),
+                                                      ct.byref(t)), "ntt_server_stage")
+        word = ct.c_uint64 if self.np_dtype == np.uint64 else ct.c_uint32
+        f = np.ctypeslib.as_array((word * n).from_address(fp.value))
+        g = np.ctypeslib.as_array((word * n).from_address(gp.value))
+        return f, g, (t.value, n)
+
+    def submit_staged(self, ticket) -> None:
+        self._nt._check(self._nt.lib.ntt_server_submit_staged(self._h, ticket[0]), "ntt_server_submit_staged")
+
+    def result(self, ticket, timeout: float = -1.0, out: np.ndarray | None = None) -> np.ndarray:
+        """Waits for the request and returns its result, copied into `out`
+        when given (a reused buffer saves the page faults of a fresh one)."""
         tid, n = ticket
-        out = np.empty(n, dtype=self.np_dtype)
+        if out is None:
+            out = np.empty(n, dtype=self.np_dtype)
+        elif out.dtype != self.np_dtype or out.shape != (n,) or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous array of %d words" % n)
         self._nt._check(self._nt.lib.ntt_server_wait(self._h, tid, out.ctypes.data, timeout), "ntt_server_wait")
         return out
 

@@ -51,6 +51,10 @@ def lib():
     L.ntt_server_create.restype = I32
     L.ntt_server_submit.argtypes = [VP, VP, VP, U32, ctypes.POINTER(U64)]
     L.ntt_server_submit.restype = I32
+    L.ntt_server_stage.argtypes = [VP, U32, VP, VP, VP]
+    L.ntt_server_stage.restype = I32
+    L.ntt_server_submit_staged.argtypes = [VP, U64]
+    L.ntt_server_submit_staged.restype = I32
     L.ntt_server_wait.argtypes = [VP, U64, VP, ctypes.c_double]
     L.ntt_server_wait.restype = I32
     L.ntt_server_stats.argtypes = [VP, VP, VP, VP, VP, U32]
@@ -225,5 +229,7 @@ def test_server_argument_validation(lib):
     t = ctypes.c_uint64()
     assert lib.ntt_server_submit(None, None, None, 4, ctypes.byref(t)) == 1
     assert lib.ntt_server_wait(None, 1, None, 0.0) == 1
+    assert lib.ntt_server_stage(None, 4, None, None, None) == 1
+    assert lib.ntt_server_submit_staged(None, 1) == 1
     assert lib.ntt_server_stats(None, None, None, None, None, 0) == 1
     lib.ntt_server_destroy(None)

@@ -124,3 +124,29 @@ def test_native_server_admission_and_shutdown():
         srv.submit(np.zeros(1 << 15, np.uint32), np.zeros(1 << 15, np.uint32))    # larger than the arena
     assert e.value.name == "NTT_E_LENGTH"
     srv.close()                                   # ten tickets still pending
+
+
+def test_native_server_zero_copy_submission():
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import NativeConvServer
+    m = si.M_U64
+    rng = np.random.default_rng(13)
+    lens = si.served_lengths(60, seed=9)
+    with NativeConvServer(m, capacity_log2=20, elem_bits=64, streams=2) as srv:
+        ops, tickets = [], []
+        for n in lens:
+            N = 1 << int(n)
+            bf, bg, t = srv.stage(N)
+            bf[...] = rng.integers(0, m, N, dtype=np.uint64)
+            bg[...] = rng.integers(0, m, N, dtype=np.uint64)
+            ops.append((bf.copy(), bg.copy()))
+            tickets.append(t)
+        with pytest.raises(nt.NttError):
+            srv.result(tickets[0], timeout=0.0)          # staged, never queued
+        for t in tickets:
+            srv.submit_staged(t)
+        with pytest.raises(nt.NttError):
+            srv.submit_staged(tickets[0])                # queued once only
+        outs = [srv.result(t, timeout=60.0) for t in tickets]
+    for (f, g), o in zip(ops, outs):
+        assert np.array_equal(o, host(nt.conv_circular(dev(f), dev(g), m)))
