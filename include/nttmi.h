@@ -269,7 +269,9 @@ ntt_status ntt_server_stats(ntt_server *srv, uint64_t *completed, double *mean_b
                             double *p99_ms, uint32_t reset);
 
 /* Finishes every queued and running request, stops the thread and frees the
- * server.  Tickets not yet waited for are released. */
+ * server.  Tickets not yet waited for are released.  No other call on the
+ * server may run concurrently with it or follow it.  The other ntt_server_*
+ * calls are safe from several threads at once. */
 void ntt_server_destroy(ntt_server *srv);
 
 /* Static description of a status code. */

@@ -466,6 +466,10 @@ class NativeConvServer:
             self._nt.lib.ntt_server_destroy(self._h)
             self._h = None
 
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self.close()
+
     def __enter__(self):
         return self
 
