@@ -908,7 +908,8 @@ ntt_status conv_crt(uint32_t log2n, const void* f, const void* g, void* h, uint3
     st = get_plan(m1, log2n, r1, l1, &p1);
     if (st == NTT_OK) st = get_plan(m2, log2n, r2, l2, &p2);
     if (st != NTT_OK) return st;
-    // residues of both convolutions, then their combination
+    // residues mod m1, then the convolution mod m2 whose final store combines
+    // both (the fused kernel's CRT store above 2^12; a combine kernel below)
     void* tmp = nullptr;
     st = get_buf(caches().tune, stream, 2 * in_bytes, &tmp);
     if (st != NTT_OK) return st;
@@ -917,10 +918,26 @@ ntt_status conv_crt(uint32_t log2n, const void* f, const void* g, void* h, uint3
     std::vector<uint64_t> off(batch);
     for (uint32_t i = 0; i < batch; ++i) off[i] = (uint64_t)i * N;
     hipStream_t s = (hipStream_t)stream;
-    st = launch_class(log2n, off, p1, 32, (const char*)f, (const char*)g, (char*)a1, s, stream);
-    if (st == NTT_OK) st = launch_class(log2n, off, p2, 32, (const char*)f, (const char*)g, (char*)a2, s, stream);
-    if (st != NTT_OK) return st;
     const uint32_t c = (uint32_t)powmod64(m1 % m2, m2 - 2, m2);   // m1^-1 mod m2
+    st = launch_class(log2n, off, p1, 32, (const char*)f, (const char*)g, (char*)a1, s, stream);
+    if (st != NTT_OK) return st;
+    if ((int)log2n > SMALL_MAX_LOG2N) {
+        const uint64_t per_wg = (uint64_t)2 * 4 << log2n;
+        uint64_t grid = (uint64_t)std::max(1, cu_count()) * std::max(1, fused_blocks_per_cu(32, (int)log2n));
+        grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, (1ull << 30) / per_wg));
+        grid = std::min<uint64_t>(grid, batch);
+        void* ws = nullptr;
+        st = get_buf(caches().work, stream, (size_t)(grid * per_wg), &ws);
+        if (st != NTT_OK) return st;
+        uint32_t* q = nullptr;
+        st = get_queue(stream, &q);
+        if (st != NTT_OK) return st;
+        const CrtStore cs{a1, (uint64_t*)h, (uint32_t)m1, c};
+        return hip_status(launch_conv_fused(32, (int)log2n, f, g, nullptr, nullptr, batch, ws, q, (uint32_t)grid,
+                                            p2->dev, s, nullptr, &cs));
+    }
+    st = launch_class(log2n, off, p2, 32, (const char*)f, (const char*)g, (char*)a2, s, stream);
+    if (st != NTT_OK) return st;
     return hip_status(launch_crt_combine(a1, a2, (uint64_t*)h, (uint64_t)batch * N, (uint32_t)m1, (uint32_t)m2, c, s));
 }
 

@@ -42,7 +42,7 @@ constexpr int small_threads(int L, int S) { return L < 16 ? S : S * (L / 16); }
 // inverted as F^(m-2) (Fermat); a zero F sets *singular (the quotient is then
 // meaningless, and the caller reports it).  F and G are forward outputs
 // (|.| <= 8m + 32 for 32-bit words, < 12 m for 64-bit words).
-enum { OP_MUL = 0, OP_DIV = 1 };
+enum { OP_MUL = 0, OP_DIV = 1, OP_CRT = 2 };   // OP_CRT: OP_MUL with the two-prime final store
 template <class W, int OP>
 __device__ __forceinline__ double spectral(double F, double G, const DevPlan& p, const ModC& M,
                                            uint32_t* singular) {
@@ -575,25 +575,44 @@ __device__ __forceinline__ ColInvIn<W, LOGN> col_inv_load(const typename W::swor
     return in;
 }
 
-template <class W, int LOGN, bool SCALE>
+template <class W, int LOGN, bool SCALE, bool CRT = false>
 __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typename W::word* x, int c0,
-                                                const DevPlan& p, const FSLds<LOGN>& L) {
+                                                const DevPlan& p, const FSLds<LOGN>& L,
+                                                const CrtStore& crt = CrtStore{}) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
-    const Buf bx(x, G::N * W::WB);
     const uint32_t off = (uint32_t)(j * G::A + c0 + s);
     double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.w[i]);
     block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
                                                   twtab<W, G::Bn>(L.coli, M));
+    if constexpr (!CRT) {
+        const Buf bx(x, G::N * W::WB);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) {
-        const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
-        st_word_s<W>(bx, W::canon(y, M), off, B::posL(0, i) * G::A);
+        for (int i = 0; i < B::E; ++i) {
+            const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
+            st_word_s<W>(bx, W::canon(y, M), off, B::posL(0, i) * G::A);
+        }
+    } else {
+        // y is this element mod m2 (= M.m) and a1 its residue mod m1: the
+        // integer in [0, m1 m2) with both residues is a1 + m1 t,
+        // t = ((y - a1) m1^-1) mod m2 (every product below 2^47)
+        const Buf ba(crt.a1, G::N * 4u), bh(crt.h, G::N * 8u);
+        const double c = (double)crt.c;
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) {
+            const uint32_t a1 = ba.ld32s(off * 4u, B::posL(0, i) * G::A * 4u);
+            const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
+            const double d = reduce(y - (double)a1, M);
+            double t = mulmod_var(d, c, M);
+            t = (t < 0.0) ? t + M.m : t;
+            t = (t >= M.m) ? t - M.m : t;
+            bh.st64((uint64_t)a1 + (uint64_t)crt.m1 * (uint64_t)t, off * 8u, B::posL(0, i) * G::A * 8u);
+        }
     }
 }
 
@@ -695,7 +714,7 @@ __global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* 
 template <class W, int LOGN, int OP = OP_MUL>
 struct FusedCfg {
     // (the deconvolution's simultaneous inversion needs more registers)
-    static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16 && OP == OP_MUL;
+    static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16 && OP != OP_DIV;
     // minimum waves per SIMD (the second __launch_bounds__ argument): four
     // for two 512-thread workgroups per CU, i.e. at most 128 VGPRs
     static constexpr int WAVES_PER_EU = TWO ? 4 : 2;
@@ -730,16 +749,19 @@ template <class W, int LOGN, bool PREFETCH, int OP = OP_MUL>
 __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, const typename W::word* gi,
                                                 typename W::word* hi, typename W::sword* Yf,
                                                 typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN>& L,
-                                                uint32_t* singular = nullptr) {
+                                                uint32_t* singular = nullptr, const CrtStore& crt = CrtStore{}) {
     using G = FS<LOGN>;
     constexpr int CL = G::A - G::SC;
+    constexpr int SOP = OP == OP_DIV ? OP_DIV : OP_MUL;   // the pointwise step
+    constexpr bool CRT = OP == OP_CRT;                    // the final store
     if constexpr (!PREFETCH) {
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(fi, Yf, c0, p, L);
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(gi, Yg, c0, p, L);
         __syncthreads();
-        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN, OP, false>(Yf, Yg, r0, p, L, singular);
+        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN, SOP, false>(Yf, Yg, r0, p, L, singular);
         __syncthreads();
-        for (int c0 = 0; c0 < G::A; c0 += G::SC) col_inv_block<W, LOGN, false>(Yf, hi, c0, p, L);
+        for (int c0 = 0; c0 < G::A; c0 += G::SC)
+            col_inv_compute<W, LOGN, false, CRT>(col_inv_load<W, LOGN>(Yf, c0), hi, c0, p, L, crt);
         __syncthreads();
     } else {
         ColIn<W, LOGN> cin = col_fwd_load<W, LOGN>(fi, 0);
@@ -763,18 +785,18 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
         RowIn<W, LOGN> rin = row_conv_load<W, LOGN>(Yf, Yg, 0);
         for (int r0 = 0; r0 < G::Bn - G::SR; r0 += G::SR) {
             const RowIn<W, LOGN> nxt = row_conv_load<W, LOGN>(Yf, Yg, r0 + G::SR);
-            row_conv_compute<W, LOGN, OP>(rin, Yf, r0, p, L, singular);
+            row_conv_compute<W, LOGN, SOP>(rin, Yf, r0, p, L, singular);
             rin = nxt;
         }
-        row_conv_compute<W, LOGN, OP>(rin, Yf, G::Bn - G::SR, p, L, singular);
+        row_conv_compute<W, LOGN, SOP>(rin, Yf, G::Bn - G::SR, p, L, singular);
         __syncthreads();
         ColInvIn<W, LOGN> iin = col_inv_load<W, LOGN>(Yf, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
             const ColInvIn<W, LOGN> nxt = col_inv_load<W, LOGN>(Yf, c0 + G::SC);
-            col_inv_compute<W, LOGN, false>(iin, hi, c0, p, L);
+            col_inv_compute<W, LOGN, false, CRT>(iin, hi, c0, p, L, crt);
             iin = nxt;
         }
-        col_inv_compute<W, LOGN, false>(iin, hi, CL, p, L);
+        col_inv_compute<W, LOGN, false, CRT>(iin, hi, CL, p, L, crt);
         __syncthreads();
     }
 }
@@ -786,7 +808,7 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
 template <class W, int LOGN, int OP = OP_MUL>
 __global__ __launch_bounds__(512, (FusedCfg<W, LOGN, OP>::WAVES_PER_EU)) void k_conv_fused(
     const typename W::word* f, const typename W::word* g, typename W::word* h, const uint64_t* __restrict__ offs,
-    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p, uint32_t* singular) {
+    uint32_t count, typename W::sword* scratch, uint32_t* queue, DevPlan p, uint32_t* singular, CrtStore crt) {
     using G = FS<LOGN>;
     __shared__ double lds[FSLds<LOGN>::WORDS];
     __shared__ uint32_t ticket;
@@ -797,8 +819,13 @@ __global__ __launch_bounds__(512, (FusedCfg<W, LOGN, OP>::WAVES_PER_EU)) void k_
         const uint32_t item = queue_take(queue, &ticket);
         if (item >= count) break;
         const uint64_t off = offs ? offs[item] : (uint64_t)item * G::N;
+        CrtStore ci = crt;
+        if constexpr (OP == OP_CRT) {
+            ci.a1 += off;
+            ci.h += off;
+        }
         fused_conv_item<W, LOGN, !FusedCfg<W, LOGN, OP>::TWO, OP>(f + off, g + off, h + off, Yf, Yg, p, L,
-                                                                 singular);
+                                                                 singular, ci);
     }
     queue_leave(queue);
 }

@@ -19,6 +19,16 @@ struct DevPlan {
     int logn, nmask;
 };
 
+// Final store of the fused convolution as the two-prime combination: a1 holds
+// the item's residues mod m1 (same element offsets as h); the convolution runs
+// mod m2 = the plan's modulus; c = m1^-1 mod m2; h receives 64-bit words.
+struct CrtStore {
+    const uint32_t* a1;
+    uint64_t* h;
+    uint32_t m1;
+    uint32_t c;
+};
+
 constexpr int SMALL_MAX_LOG2N = 12;
 // Four-step split of N = 2^n above 2^SMALL_MAX_LOG2N: N = A B with A = 2^fs_la(n)
 // (row length) and B = 2^(n - fs_la(n)) (column length).  Shared by the kernels
@@ -51,9 +61,11 @@ hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, voi
 // before the launch and zero again after it (launches sharing a queue must be
 // ordered, e.g. on one stream).  singular != null selects the deconvolution
 // (h = g / f in the spectrum; a zero coefficient of f sets *singular).
+// crt != null (32-bit words): the result is stored as the combination with
+// crt->a1 into crt->h (h itself is not written).
 hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
                              uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
-                             hipStream_t st, uint32_t* singular = nullptr);
+                             hipStream_t st, uint32_t* singular = nullptr, const CrtStore* crt = nullptr);
 int fused_blocks_per_cu(int wbits, int logn, int div = 0);
 // One launch for a batch of uneven lengths <= 2^multi_max_log2n(wbits).  tasks:
 // device array of {uint64 first item; uint32 log2n; uint32 item count} listed

@@ -6,14 +6,14 @@ namespace nttmi {
 template <class W, int OP>
 static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, const uint64_t* offs,
                                uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
-                               hipStream_t st, uint32_t* singular) {
+                               hipStream_t st, uint32_t* singular, CrtStore crt = CrtStore{}) {
     using T = typename W::word;
     using SW = typename W::sword;
     switch (logn) {
 #define CASE(n)                                                                                                   \
     case n:                                                                                                       \
         hipLaunchKernelGGL((k_conv_fused<W, n, OP>), dim3(grid), dim3(FS<n>::T), 0, st, (const T*)f, (const T*)g, \
-                           (T*)h, offs, count, (SW*)scratch, queue, p, singular);                                 \
+                           (T*)h, offs, count, (SW*)scratch, queue, p, singular, crt);                            \
         return hipGetLastError();
         NTT_LARGE_CASES(CASE)
 #undef CASE
@@ -24,8 +24,12 @@ static hipError_t conv_fused_t(int logn, const void* f, const void* g, void* h, 
 
 hipError_t launch_conv_fused(int wbits, int logn, const void* f, const void* g, void* h, const uint64_t* offs,
                              uint32_t count, void* scratch, uint32_t* queue, uint32_t grid, const DevPlan& p,
-                             hipStream_t st, uint32_t* singular) {
+                             hipStream_t st, uint32_t* singular, const CrtStore* crt) {
     if (count == 0) return hipSuccess;
+    if (crt) {
+        if (wbits != 32 || singular) return hipErrorInvalidValue;
+        return conv_fused_t<W32, OP_CRT>(logn, f, g, h, offs, count, scratch, queue, grid, p, st, nullptr, *crt);
+    }
     if (singular)
         return wbits == 32
                    ? conv_fused_t<W32, OP_DIV>(logn, f, g, h, offs, count, scratch, queue, grid, p, st, singular)
