@@ -588,6 +588,13 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
     double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.w[i]);
+    // the first residues, loaded ahead of the transform that hides their latency
+    uint32_t a1v[CRT ? B::E : 1];
+    if constexpr (CRT) {
+        const Buf ba(crt.a1, G::N * 4u);
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) a1v[i] = ba.ld32s(off * 4u, B::posL(0, i) * G::A * 4u);
+    }
     block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
                                                   twtab<W, G::Bn>(L.coli, M));
     if constexpr (!CRT) {
@@ -601,11 +608,11 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
         // y is this element mod m2 (= M.m) and a1 its residue mod m1: the
         // integer in [0, m1 m2) with both residues is a1 + m1 t,
         // t = ((y - a1) m1^-1) mod m2 (every product below 2^47)
-        const Buf ba(crt.a1, G::N * 4u), bh(crt.h, G::N * 8u);
+        const Buf bh(crt.h, G::N * 8u);
         const double c = (double)crt.c;
 #pragma unroll
         for (int i = 0; i < B::E; ++i) {
-            const uint32_t a1 = ba.ld32s(off * 4u, B::posL(0, i) * G::A * 4u);
+            const uint32_t a1 = a1v[i];
             const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
             const double d = reduce(y - (double)a1, M);
             double t = mulmod_var(d, c, M);
