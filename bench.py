@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt", "conv2d", "u64"], default="batch",
                     help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
                          "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
-    ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests")
+    ap.add_argument("--requests", type=int, default=4000, help="serve: timed requests")
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (reference kernel for the HBM byte counters)")
