@@ -151,8 +151,8 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
  * of N = 2^log2n contiguous elements; row r of g solves row r of f and h.
  * Same requirements on m, N and root as conv_circular (NTT_FLAG_EULER
  * applies).  Returns NTT_E_SINGULAR when some forward(f) coefficient of some
- * row is zero (g is then unspecified).  Synchronises the stream (it reads that
- * verdict back), so it is not for use while the stream is being captured.
+ * row is zero (g is then unspecified).  Synchronises the stream (it reads the
+ * singular flag back), so it is not for use while the stream is being captured.
  * g may equal h (in place); partial overlap is NTT_E_ARG. */
 ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
                            const void *f, const void *h, void *g, uint32_t batch,
