@@ -14,7 +14,9 @@
  * C ABI.  No C++ types and no exceptions cross this boundary.  All pointers
  * named f, g, h, x, X are DEVICE pointers to little-endian unsigned words of
  * elem_bits bits, owned by the caller; the library keeps none of them after
- * a call returns.  `stream` is a hipStream_t (NULL = the null stream).
+ * a call returns (the served-form calls ntt_copy_batch and ntt_server_* state
+ * their own host or device pointers).  `stream` is a hipStream_t (NULL = the
+ * null stream).
  *
  * Results are exact residues in canonical form [0, m) (Appendix A).  Inputs
  * may hold any elem_bits-bit value; it is read modulo m.
