@@ -150,3 +150,45 @@ def test_native_server_zero_copy_submission():
         outs = [srv.result(t, timeout=60.0) for t in tickets]
     for (f, g), o in zip(ops, outs):
         assert np.array_equal(o, host(nt.conv_circular(dev(f), dev(g), m)))
+
+
+def test_native_server_cross_thread_waits():
+    # four submitting threads and four waiting threads, tickets handed over
+    # through a queue: every result equals the same convolution run alone
+    import queue
+    import threading
+
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import NativeConvServer
+    m = si.M_13631489
+    rng = np.random.default_rng(14)
+    reqs = [(rng.integers(0, m, 1 << int(n), dtype=np.uint32), rng.integers(0, m, 1 << int(n), dtype=np.uint32))
+            for n in rng.integers(4, 15, 240)]
+    handoff = queue.Queue()
+    results = {}
+    with NativeConvServer(m, capacity_log2=19, elem_bits=32, streams=3, max_batch=64) as srv:
+        def submitter(k):
+            for i in range(k, len(reqs), 4):
+                handoff.put((i, srv.submit(*reqs[i])))
+
+        def waiter():
+            while True:
+                item = handoff.get()
+                if item is None:
+                    return
+                i, t = item
+                results[i] = srv.result(t, timeout=60.0)
+
+        subs = [threading.Thread(target=submitter, args=(k,)) for k in range(4)]
+        waits = [threading.Thread(target=waiter) for _ in range(4)]
+        for t in subs + waits:
+            t.start()
+        for t in subs:
+            t.join()
+        for _ in waits:
+            handoff.put(None)
+        for t in waits:
+            t.join()
+    assert len(results) == len(reqs)
+    for i, (f, g) in enumerate(reqs):
+        assert np.array_equal(results[i], host(nt.conv_circular(dev(f), dev(g), m))), i
