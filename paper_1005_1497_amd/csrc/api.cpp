@@ -1001,20 +1001,24 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     if (!d->log2n || !d->offset || !f || !g || !h) return NTT_E_ARG;
     const uint32_t cnt = d->count;
     // items: lengths within the root's order, no two items overlapping
-    std::vector<std::pair<uint64_t, uint64_t>> ext(cnt);
     uint64_t total = 0;
+    bool ascending = true;   // items listed in address order: overlap is checked in one pass
     for (uint32_t i = 0; i < cnt; ++i) {
         const uint32_t n = d->log2n[i];
         if (n > root_log2order) return NTT_E_LENGTH;
         if (n > (uint32_t)MAX_LOG2N) return NTT_E_UNSUPPORTED;
         const uint64_t len = 1ull << n;
         if (d->offset[i] > (UINT64_MAX >> 3) - len) return NTT_E_ARG;
-        ext[i] = std::make_pair(d->offset[i], d->offset[i] + len);
+        if (i > 0 && d->offset[i] < d->offset[i - 1] + (1ull << d->log2n[i - 1])) ascending = false;
         total = std::max(total, d->offset[i] + len);
     }
-    std::sort(ext.begin(), ext.end());
-    for (uint32_t i = 1; i < cnt; ++i)
-        if (ext[i].first < ext[i - 1].second) return NTT_E_ARG;
+    if (!ascending) {
+        std::vector<std::pair<uint64_t, uint64_t>> ext(cnt);
+        for (uint32_t i = 0; i < cnt; ++i) ext[i] = std::make_pair(d->offset[i], d->offset[i] + (1ull << d->log2n[i]));
+        std::sort(ext.begin(), ext.end());
+        for (uint32_t i = 1; i < cnt; ++i)
+            if (ext[i].first < ext[i - 1].second) return NTT_E_ARG;
+    }
     const size_t bytes = (size_t)total * (elem_bits / 8);
     if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
     if (flags & NTT_FLAG_CHECK_RANGE) {
@@ -1031,7 +1035,18 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
 
     // length classes
     std::map<uint32_t, std::vector<uint64_t>> cls;
-    for (uint32_t i = 0; i < cnt; ++i) cls[d->log2n[i]].push_back(d->offset[i]);
+    {
+        // count per length first, then fill: one allocation per length
+        uint32_t per[MAX_LOG2N + 1] = {0};
+        for (uint32_t i = 0; i < cnt; ++i) ++per[d->log2n[i]];
+        std::vector<uint64_t>* slot[MAX_LOG2N + 1] = {nullptr};
+        for (int n = 0; n <= MAX_LOG2N; ++n)
+            if (per[n]) {
+                slot[n] = &cls[(uint32_t)n];
+                slot[n]->reserve(per[n]);
+            }
+        for (uint32_t i = 0; i < cnt; ++i) slot[d->log2n[i]]->push_back(d->offset[i]);
+    }
     std::map<uint32_t, const Plan*> plans;
     for (auto& kv : cls) {
         const uint32_t n = kv.first;
