@@ -688,6 +688,19 @@ __global__ __launch_bounds__(512) void k_fs_col_fwd(const typename W::word* x, t
     const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
     col_fwd_block<W, LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
 }
+// Column phase of both operands in one launch: grid.y = 2 * items, the first
+// half f (into Y_f), the second g (into Y_g = Y_f + N).
+template <class W, int LOGN>
+__global__ __launch_bounds__(512) void k_fs_col_fwd2(const typename W::word* f, const typename W::word* g,
+                                                     typename W::sword* Y, uint64_t item_stride, uint64_t ystride,
+                                                     uint32_t items, DevPlan p) {
+    __shared__ double lds[FSLds<LOGN>::WORDS];
+    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    const uint32_t second = blockIdx.y >= items ? 1u : 0u;
+    const uint32_t item = blockIdx.y - second * items;
+    col_fwd_block<W, LOGN>((second ? g : f) + item * item_stride, Y + item * ystride + second * FS<LOGN>::N,
+                           blockIdx.x * FS<LOGN>::SC, p, L);
+}
 template <class W, int LOGN, int OP>
 __global__ __launch_bounds__(512) void k_fs_row_conv(typename W::sword* Yf, const typename W::sword* Yg,
                                                      uint64_t ystride, DevPlan p, uint32_t* singular) {

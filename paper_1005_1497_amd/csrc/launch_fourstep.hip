@@ -16,10 +16,15 @@ static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* 
         const uint64_t ys = 2ull * G::N;                                                                          \
         SW* Yf = (SW*)scratch;                                                                                    \
         SW* Yg = Yf + G::N;                                                                                       \
-        hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)f, Yf,     \
-                           item_stride, ys, p);                                                                   \
-        hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)g, Yg,     \
-                           item_stride, ys, p);                                                                   \
+        if (2ull * items <= 65535) {                                                                              \
+            hipLaunchKernelGGL((k_fs_col_fwd2<W, n>), dim3(G::A / G::SC, 2 * items), dim3(G::T), 0, st,            \
+                               (const T*)f, (const T*)g, Yf, item_stride, ys, items, p);                          \
+        } else {                                                                                                  \
+            hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)f,   \
+                               Yf, item_stride, ys, p);                                                           \
+            hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, items), dim3(G::T), 0, st, (const T*)g,   \
+                               Yg, item_stride, ys, p);                                                           \
+        }                                                                                                         \
         if (singular)                                                                                             \
             hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_DIV>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
                                (const SW*)Yg, ys, p, singular);                                                   \
