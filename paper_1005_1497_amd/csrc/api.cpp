@@ -973,16 +973,22 @@ ntt_status conv2d_circular(uint64_t m, uint32_t log2r, uint32_t log2c, uint64_t 
     hipStream_t s = (hipStream_t)stream;
     const int w = (int)elem_bits;
     // forward: rows of f (length C), transpose, rows again (length R); the same
-    // for g (h serves as its buffer once f and g have been read); product;
-    // inverse along R (with R^-1), transpose back, inverse along C (with C^-1)
+    // for g (h serves as its buffer once f and g have been read); product
+    // (formed on load by the next pass for R <= 2^12); inverse along R (with
+    // R^-1), transpose back, inverse along C (with C^-1)
     st = ntt_rows(pc, elem_bits, log2c, false, f, A, R, stream);
     if (st == NTT_OK) st = hip_status(launch_transpose(w, A, B, R, C, s));
     if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, false, B, B, C, stream);
     if (st == NTT_OK) st = ntt_rows(pc, elem_bits, log2c, false, g, A, R, stream);
     if (st == NTT_OK) st = hip_status(launch_transpose(w, A, H, R, C, s));
     if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, false, H, H, C, stream);
-    if (st == NTT_OK) st = hip_status(launch_pointwise_mul(w, B, H, B, n, pr->dev.M, s));
-    if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, true, B, B, C, stream);
+    if ((int)log2r <= SMALL_MAX_LOG2N) {
+        // the product formed on load by the first inverse pass
+        if (st == NTT_OK) st = hip_status(launch_ntt_small(w, (int)log2r, true, B, B, C, pr->dev, s, H));
+    } else {
+        if (st == NTT_OK) st = hip_status(launch_pointwise_mul(w, B, H, B, n, pr->dev.M, s));
+        if (st == NTT_OK) st = ntt_rows(pr, elem_bits, log2r, true, B, B, C, stream);
+    }
     if (st == NTT_OK) st = hip_status(launch_transpose(w, B, A, C, R, s));
     if (st == NTT_OK) st = ntt_rows(pc, elem_bits, log2c, true, A, H, R, stream);
     return st;

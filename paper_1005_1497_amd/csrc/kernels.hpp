@@ -176,9 +176,11 @@ __global__ __launch_bounds__(256, (small_waves_per_eu(L, OP, W::WB))) void k_con
                                  singular);
 }
 
-template <class W, int L, bool INV>
+// MULIN (inverse only): the input is the pointwise product x y mod m, formed
+// on load (the 2-D convolution's product step fused into its first inverse pass).
+template <class W, int L, bool INV, bool MULIN = false>
 __global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, typename W::word* X, uint32_t batch,
-                                                   DevPlan p) {
+                                                   DevPlan p, const typename W::word* y) {
     constexpr int S = small_s(L);
     using B = Blk<L, S, POS_FAST>;
     __shared__ double lds[B::LDS_DOUBLES];
@@ -191,6 +193,10 @@ __global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, ty
     double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(x[off + B::pos0(j, i)], M);
+    if constexpr (MULIN) {
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) v[i] = W::mul_var(v[i], W::load_reduce(y[off + B::pos0(j, i)], M), M);
+    }
     block_dft<W, L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M);
     if (valid) {
 #pragma unroll

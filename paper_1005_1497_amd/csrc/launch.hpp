@@ -50,7 +50,7 @@ hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, 
                              uint32_t count, const DevPlan& p, hipStream_t st, int tile = SMALL_TILE_256,
                              uint32_t* singular = nullptr);
 hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
-                            hipStream_t st);
+                            hipStream_t st, const void* y = nullptr);
 // scratch: items * 2N scratch words (conv), batch * N (ntt); scratch words are wbits/8 bytes
 hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
                                 uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,

@@ -39,18 +39,21 @@ hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, 
 
 template <class W>
 static hipError_t ntt_small_t(int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
-                              hipStream_t st) {
+                              hipStream_t st, const void* y) {
     using T = typename W::word;
     switch (logn) {
 #define CASE(n)                                                                                                   \
     case n: {                                                                                                     \
         const uint32_t S = small_s(1 << n);                                                                       \
-        if (inv)                                                                                                  \
+        if (inv && y)                                                                                             \
+            hipLaunchKernelGGL((k_ntt_small<W, 1 << n, true, true>), dim3((batch + S - 1) / S), dim3(256), 0, st, \
+                               (const T*)x, (T*)X, batch, p, (const T*)y);                                        \
+        else if (inv)                                                                                             \
             hipLaunchKernelGGL((k_ntt_small<W, 1 << n, true>), dim3((batch + S - 1) / S), dim3(256), 0, st,       \
-                               (const T*)x, (T*)X, batch, p);                                                     \
+                               (const T*)x, (T*)X, batch, p, nullptr);                                            \
         else                                                                                                      \
             hipLaunchKernelGGL((k_ntt_small<W, 1 << n, false>), dim3((batch + S - 1) / S), dim3(256), 0, st,      \
-                               (const T*)x, (T*)X, batch, p);                                                     \
+                               (const T*)x, (T*)X, batch, p, nullptr);                                            \
         return hipGetLastError();                                                                                 \
     }
         NTT_SMALL_CASES(CASE)
@@ -61,10 +64,11 @@ static hipError_t ntt_small_t(int logn, bool inv, const void* x, void* X, uint32
 }
 
 hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
-                            hipStream_t st) {
+                            hipStream_t st, const void* y) {
     if (batch == 0) return hipSuccess;
-    return wbits == 32 ? ntt_small_t<W32>(logn, inv, x, X, batch, p, st)
-                       : ntt_small_t<W64>(logn, inv, x, X, batch, p, st);
+    if (y && !inv) return hipErrorInvalidValue;
+    return wbits == 32 ? ntt_small_t<W32>(logn, inv, x, X, batch, p, st, y)
+                       : ntt_small_t<W64>(logn, inv, x, X, batch, p, st, y);
 }
 
 }  // namespace nttmi
