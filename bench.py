@@ -110,8 +110,8 @@ def main():
                     help="only copy a 1 GiB device buffer 4 times (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the batch would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a batch would shard by items, one process per GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.calibrate_copy:

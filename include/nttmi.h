@@ -49,7 +49,7 @@ typedef enum {
     NTT_E_RANGE = 5,        /* an operand >= m, only with NTT_FLAG_CHECK_RANGE */
     NTT_E_NOMEM = 6,        /* device or host allocation failed */
     NTT_E_DEVICE = 7,       /* a HIP runtime call or kernel launch failed */
-    NTT_E_UNSUPPORTED = 8,  /* a valid request this build does not implement (64-bit
+    NTT_E_UNSUPPORTED = 8,  /* a valid request the library does not implement (64-bit
                                words: m >= 2^46; lengths above 2^22) */
     NTT_E_SINGULAR = 9      /* conv_deconvolve: a spectral coefficient of the divisor
                                is zero, so no unique quotient exists */

@@ -1154,7 +1154,7 @@ const char* ntt_status_string(ntt_status s) {
         case NTT_E_RANGE: return "an operand is not below m";
         case NTT_E_NOMEM: return "out of memory";
         case NTT_E_DEVICE: return "HIP runtime or launch failure";
-        case NTT_E_UNSUPPORTED: return "valid request not supported by this build";
+        case NTT_E_UNSUPPORTED: return "valid request not supported by the library";
         case NTT_E_SINGULAR: return "a spectral coefficient of the divisor is zero (no unique quotient)";
     }
     return "unknown status";
