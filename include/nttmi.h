@@ -51,8 +51,9 @@ typedef enum {
     NTT_E_DEVICE = 7,       /* a HIP runtime call or kernel launch failed */
     NTT_E_UNSUPPORTED = 8,  /* a valid request the library does not implement (64-bit
                                words: m >= 2^46; lengths above 2^22) */
-    NTT_E_SINGULAR = 9      /* conv_deconvolve: a spectral coefficient of the divisor
+    NTT_E_SINGULAR = 9,     /* conv_deconvolve: a spectral coefficient of the divisor
                                is zero, so no unique quotient exists */
+    NTT_E_TIMEOUT = 10      /* ntt_server_wait: the time limit passed first */
 } ntt_status;
 
 /* Flags (bitwise OR). */
@@ -259,9 +260,9 @@ ntt_status ntt_server_submit_staged(ntt_server *srv, uint64_t ticket);
 
 /* Waits up to timeout_s seconds (negative: no limit) for the request, copies
  * its 2^log2n result words to h (host) and releases the ticket.  NTT_E_ARG: an
- * unknown ticket or a staged one never queued; NTT_E_DEVICE: its batch failed
- * (the ticket is released);
- * NTT_E_UNSUPPORTED: the time ran out (the ticket stays valid). */
+ * unknown ticket, a staged one never queued, or a ticket another thread is
+ * waiting for at the same time; NTT_E_DEVICE: its batch failed (the ticket is
+ * released); NTT_E_TIMEOUT: the time ran out (the ticket stays valid). */
 ntt_status ntt_server_wait(ntt_server *srv, uint64_t ticket, void *h, double timeout_s);
 
 /* Completed requests since creation or the last reset, the mean requests per

@@ -34,6 +34,7 @@ LIB_PATH = os.path.join(_HERE, "libnttmi.so")
 STATUS = {
     0: "NTT_OK", 1: "NTT_E_ARG", 2: "NTT_E_MODULUS", 3: "NTT_E_LENGTH", 4: "NTT_E_ROOT",
     5: "NTT_E_RANGE", 6: "NTT_E_NOMEM", 7: "NTT_E_DEVICE", 8: "NTT_E_UNSUPPORTED", 9: "NTT_E_SINGULAR",
+    10: "NTT_E_TIMEOUT",
 }
 FLAG_CHECK_RANGE = 0x1
 FLAG_PER_ITEM = 0x2

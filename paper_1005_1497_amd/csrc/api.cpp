@@ -1156,6 +1156,7 @@ const char* ntt_status_string(ntt_status s) {
         case NTT_E_DEVICE: return "HIP runtime or launch failure";
         case NTT_E_UNSUPPORTED: return "valid request not supported by the library";
         case NTT_E_SINGULAR: return "a spectral coefficient of the divisor is zero (no unique quotient)";
+        case NTT_E_TIMEOUT: return "the time limit passed before the request finished";
     }
     return "unknown status";
 }

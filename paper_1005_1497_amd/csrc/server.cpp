@@ -109,6 +109,7 @@ struct Req {
     size_t staging_bytes = 0;
     Clock::time_point arrival;
     int state = Q_QUEUED;
+    bool waiting = false;   // a thread is in ntt_server_wait on this ticket
 };
 
 struct Batch {
@@ -392,12 +393,16 @@ ntt_status ntt_server_wait(ntt_server* s, uint64_t ticket, void* h, double timeo
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return NTT_E_ARG;
     Req* r = it->second;
-    if (r->state == Q_STAGED) return NTT_E_ARG;   // never queued
+    // never queued, or a second waiter (the first releases the request, which
+    // the second would then read)
+    if (r->state == Q_STAGED || r->waiting) return NTT_E_ARG;
+    r->waiting = true;
     auto ready = [r] { return r->state == Q_DONE || r->state == Q_FAILED; };
     if (timeout_s < 0) {
         s->cv_done.wait(lk, ready);
     } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
-        return NTT_E_UNSUPPORTED;
+        r->waiting = false;
+        return NTT_E_TIMEOUT;
     }
     s->reqs.erase(it);
     lk.unlock();

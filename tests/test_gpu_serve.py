@@ -192,3 +192,41 @@ def test_native_server_cross_thread_waits():
     assert len(results) == len(reqs)
     for i, (f, g) in enumerate(reqs):
         assert np.array_equal(results[i], host(nt.conv_circular(dev(f), dev(g), m))), i
+
+
+def test_native_server_one_waiter_per_ticket_and_timeout():
+    # two threads wait for the same ticket: one gets the result, the other
+    # NTT_E_ARG (the ticket is taken, or already released); a wait whose time
+    # runs out reports NTT_E_TIMEOUT and leaves the ticket valid
+    import threading
+
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import NativeConvServer
+    m = si.M_13631489
+    rng = np.random.default_rng(15)
+    f, g = (rng.integers(0, m, 1 << 18, dtype=np.uint32) for _ in range(2))
+    want = host(nt.conv_circular(dev(f), dev(g), m))
+    with NativeConvServer(m, capacity_log2=19, elem_bits=32, streams=2) as srv:
+        t = srv.submit(f, g)
+        try:
+            got = srv.result(t, timeout=0.0)
+        except nt.NttError as e:
+            assert e.name == "NTT_E_TIMEOUT"
+            got = None
+        if got is None:
+            outcome = {}
+
+            def waiter(k):
+                try:
+                    outcome[k] = srv.result(t, timeout=60.0)
+                except nt.NttError as e:
+                    outcome[k] = e.name
+            ths = [threading.Thread(target=waiter, args=(k,)) for k in range(2)]
+            for th in ths:
+                th.start()
+            for th in ths:
+                th.join()
+            wins = [v for v in outcome.values() if isinstance(v, np.ndarray)]
+            assert len(wins) == 1 and sorted(v for v in outcome.values() if isinstance(v, str)) == ["NTT_E_ARG"]
+            got = wins[0]
+        assert np.array_equal(got, want)
