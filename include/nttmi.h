@@ -266,8 +266,9 @@ ntt_status ntt_server_submit_staged(ntt_server *srv, uint64_t ticket);
 ntt_status ntt_server_wait(ntt_server *srv, uint64_t ticket, void *h, double timeout_s);
 
 /* Completed requests since creation or the last reset, the mean requests per
- * batch, and the p50 / p99 of submit-to-completion latency in milliseconds
- * (completion as the scheduler observes it).  reset != 0 clears them. */
+ * batch, and the p50 / p99 of submit-to-completion latency in milliseconds over
+ * the last 2^20 completed requests (completion as the scheduler observes it).
+ * reset != 0 clears them. */
 ntt_status ntt_server_stats(ntt_server *srv, uint64_t *completed, double *mean_batch, double *p50_ms,
                             double *p99_ms, uint32_t reset);
 

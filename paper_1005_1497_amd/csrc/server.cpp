@@ -141,9 +141,18 @@ struct ntt_server {
     bool stop = false;
     std::thread th;
 
-    // statistics
+    // statistics: the latencies of the last LAT_WINDOW completed requests (a
+    // ring, so that a long-running server holds a bounded amount)
+    static constexpr size_t LAT_WINDOW = size_t(1) << 20;
     std::vector<double> lat_ms;
-    uint64_t batches = 0, batched_reqs = 0;
+    size_t lat_next = 0;
+    uint64_t completed = 0, batches = 0, batched_reqs = 0;
+    void record_latency(double ms) {
+        if (lat_ms.size() < LAT_WINDOW) lat_ms.push_back(ms);
+        else lat_ms[lat_next] = ms;
+        lat_next = (lat_next + 1) % LAT_WINDOW;
+        completed += 1;
+    }
 
     void run();
     bool launch(std::vector<Req*>& adm);
@@ -240,8 +249,7 @@ void ntt_server::run() {
             for (Req* r : inflight[i].reqs) {
                 buddy.release(r->off, (int)r->log2n);
                 r->state = q == hipSuccess ? Q_DONE : Q_FAILED;
-                if (q == hipSuccess)
-                    lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->arrival).count());
+                if (q == hipSuccess) record_latency(std::chrono::duration<double, std::milli>(now - r->arrival).count());
             }
             (void)hipEventDestroy(inflight[i].ev);
             inflight.erase(inflight.begin() + (long)i);
@@ -427,12 +435,14 @@ ntt_status ntt_server_stats(ntt_server* s, uint64_t* completed, double* mean_bat
         const double fr = x - (double)i;
         return i + 1 < v.size() ? v[i] * (1 - fr) + v[i + 1] * fr : v[i];
     };
-    if (completed) *completed = v.size();
+    if (completed) *completed = s->completed;
     if (mean_batch) *mean_batch = s->batches ? (double)s->batched_reqs / (double)s->batches : 0.0;
     if (p50_ms) *p50_ms = pct(0.50);
     if (p99_ms) *p99_ms = pct(0.99);
     if (reset) {
         s->lat_ms.clear();
+        s->lat_next = 0;
+        s->completed = 0;
         s->batches = 0;
         s->batched_reqs = 0;
     }

@@ -109,10 +109,15 @@ class _Batch:
     launched: float
 
 
+# Statistics and the admission log keep the most recent entries only, so that
+# a long-running server holds a bounded amount.
+STATS_WINDOW = 1 << 20
+
+
 @dataclass
 class ServeStats:
-    latencies: list = field(default_factory=list)
-    batch_sizes: list = field(default_factory=list)
+    latencies: collections.deque = field(default_factory=lambda: collections.deque(maxlen=STATS_WINDOW))
+    batch_sizes: collections.deque = field(default_factory=lambda: collections.deque(maxlen=STATS_WINDOW))
     peak_used: int = 0
     peak_inflight: int = 0
     completed: int = 0
@@ -244,7 +249,7 @@ class ConvServer:
         self._stop = False
         self._thread = None
         self._outstanding = 0       # submitted and not yet completed, failed or cancelled
-        self.admission_log = []     # request ids in admission order
+        self.admission_log = collections.deque(maxlen=STATS_WINDOW)     # request ids in admission order (the latest)
 
     # ------------------------------------------------------------ client side
     def _log2_len(self, n: int) -> int:
