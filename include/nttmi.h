@@ -281,6 +281,15 @@ void ntt_server_destroy(ntt_server *srv);
 /* Static description of a status code. */
 const char *ntt_status_string(ntt_status s);
 
+/* Frees the workspaces, work queue and staging ring the library holds for
+ * `stream` on the current device, after waiting for the stream.  Call it
+ * before destroying a stream the library has used: otherwise they stay until
+ * ntt_release_caches, and a later stream that receives the same handle would
+ * share them with work still pending on the old one.  Other calls on the same
+ * stream must not run concurrently, and graphs captured on it before must not
+ * be replayed after it. */
+void ntt_release_stream(void *stream);
+
 /* Frees every cached plan, workspace, descriptor and staging slot (waits for
  * the device first).  No other call of this library may run concurrently, and
  * graphs captured before it must not be replayed after it. */

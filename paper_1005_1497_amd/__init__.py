@@ -46,7 +46,8 @@ FLAG_TRANSIENT = 0x20
 EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "conv_crt",
            "conv2d_circular",
            "ntt_default_root",
-           "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches")
+           "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches",
+           "ntt_release_stream")
 
 
 class NttError(RuntimeError):
@@ -114,6 +115,8 @@ def _load():
     L.ntt_status_string.restype = ctypes.c_char_p
     L.ntt_release_caches.argtypes = []
     L.ntt_release_caches.restype = None
+    L.ntt_release_stream.argtypes = [VP]
+    L.ntt_release_stream.restype = None
     return L
 
 
@@ -348,3 +351,9 @@ def conv_batched(f: torch.Tensor, g: torch.Tensor, desc, m: int, root: int = 2, 
 
 def release_caches() -> None:
     lib.ntt_release_caches()
+
+
+def release_stream(stream) -> None:
+    """Frees the library's workspaces for `stream` (a torch stream), after
+    waiting for it; call before the stream is dropped."""
+    lib.ntt_release_stream(_stream(stream))

@@ -1161,6 +1161,8 @@ const char* ntt_status_string(ntt_status s) {
     return "unknown status";
 }
 
+void ntt_release_stream(void* stream) { nttmi::release_stream_caches(stream); }
+
 void ntt_release_caches(void) {
     Caches& c = caches();
     std::lock_guard<std::mutex> g(c.mu);

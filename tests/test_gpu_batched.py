@@ -252,3 +252,31 @@ def test_first_call_on_fresh_streams_after_release(nt):
         o = host(out)
         for n, off in zip(lengths, offs):
             assert np.array_equal(o[off:off + (1 << n)], ref[off:off + (1 << n)]), (rep, n)
+
+
+def test_release_stream_then_reuse(nt):
+    # ntt_release_stream frees a stream's workspaces and work queue; the next
+    # call on that stream creates them again and gives the same results (also
+    # a stream the library never used may be released)
+    lengths = [16] * 6 + [13, 7, 15]
+    offs = si.offsets(lengths)
+    rng = np.random.default_rng(43)
+    S = int(offs[-1]) + (1 << lengths[-1])
+    f = dev(rng.integers(0, M, S, dtype=np.uint32))
+    g = dev(rng.integers(0, M, S, dtype=np.uint32))
+    desc = nt.BatchDesc(lengths, offs)
+    ref = host(nt.conv_batched(f, g, desc, M))
+    fh, gh = host(f), host(g)
+    for k, idx in ((7, np.arange(1 << 7)), (6, np.array([0, 1, 4095, 8191]))):
+        o, n = int(offs[k]), 1 << lengths[k]
+        got = ref[o:o + n][idx]
+        assert np.array_equal(got, oracle.conv_entries(fh[o:o + n], gh[o:o + n], M, idx).astype(got.dtype)), k
+    nt.release_stream(torch.cuda.Stream())
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        out = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            nt.conv_batched(f, g, desc, M, out=out, stream=s)
+        nt.release_stream(s)
+        assert np.array_equal(host(out), ref), rep
