@@ -511,21 +511,14 @@ ntt_status ntt_any(bool inv, uint64_t m, uint32_t log2n, uint64_t root, uint32_t
 
 // One launch for the items of one length class: the LDS kernel below 2^13,
 // the persistent fused four-step kernel above.
-ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan* p, uint32_t elem_bits,
-                        const char* F, const char* G, char* H, hipStream_t s, void* stream,
-                        uint8_t form = CF_DEFAULT, bool transient = false) {
+// c items of length 2^n: at offsets base + i 2^n (doffs null), else at the
+// device offsets doffs[i] (base 0).
+ntt_status launch_items(uint32_t n, uint32_t c, uint64_t base, const uint64_t* doffs, const Plan* p,
+                        uint32_t elem_bits, const char* F, const char* G, char* H, hipStream_t s, void* stream,
+                        uint8_t form) {
     const size_t wb = elem_bits / 8;
-    const uint32_t c = (uint32_t)off.size();
-    // contiguous uniform run: offsets base + i N, no table needed
-    bool contiguous = true;
-    for (uint32_t i = 1; i < c && contiguous; ++i) contiguous = off[i] == off[0] + ((uint64_t)i << n);
-    const uint64_t base = contiguous ? off[0] : 0;
-    const uint64_t* doffs = nullptr;
+    const bool contiguous = doffs == nullptr;
     ntt_status st = NTT_OK;
-    if (!contiguous) {
-        st = get_desc(off, transient, stream, &doffs);
-        if (st != NTT_OK) return st;
-    }
     if ((int)n <= SMALL_MAX_LOG2N)
         return hip_status(launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c,
                                             p->dev, s, form == CF_SMALL_WAVE ? SMALL_TILE_WAVE : SMALL_TILE_256));
@@ -556,6 +549,21 @@ ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan
     if (st != NTT_OK) return st;
     return hip_status(launch_conv_fused((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c,
                                         ws, q, (uint32_t)grid, p->dev, s));
+}
+
+ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan* p, uint32_t elem_bits,
+                        const char* F, const char* G, char* H, hipStream_t s, void* stream,
+                        uint8_t form = CF_DEFAULT, bool transient = false) {
+    const uint32_t c = (uint32_t)off.size();
+    // contiguous uniform run: offsets base + i N, no table needed
+    bool contiguous = true;
+    for (uint32_t i = 1; i < c && contiguous; ++i) contiguous = off[i] == off[0] + ((uint64_t)i << n);
+    const uint64_t* doffs = nullptr;
+    if (!contiguous) {
+        const ntt_status st = get_desc(off, transient, stream, &doffs);
+        if (st != NTT_OK) return st;
+    }
+    return launch_items(n, c, contiguous ? off[0] : 0, doffs, p, elem_bits, F, G, H, s, stream, form);
 }
 
 // One persistent launch for every class of length <= 2^nmax.  The task list
@@ -660,6 +668,14 @@ std::vector<uint64_t> shape_key(uint64_t m, uint32_t elem_bits, const std::map<u
         k.push_back(((uint64_t)kv.first << 32) | b);
     }
     return k;
+}
+
+std::vector<uint64_t> shape_key_uniform(uint64_t m, uint32_t elem_bits, uint32_t n, uint64_t count) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    uint64_t b = 0;
+    while (count >>= 1) ++b;
+    return {(uint64_t)dev, m, elem_bits, ((uint64_t)n << 32) | b};
 }
 
 bool lookup_form(const std::vector<uint64_t>& key, BatchForm* out) {
@@ -1009,13 +1025,18 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     // items: lengths within the root's order, no two items overlapping
     uint64_t total = 0;
     bool ascending = true;   // items listed in address order: overlap is checked in one pass
+    bool packed = true;      // one length, items back to back in order
     for (uint32_t i = 0; i < cnt; ++i) {
         const uint32_t n = d->log2n[i];
         if (n > root_log2order) return NTT_E_LENGTH;
         if (n > (uint32_t)MAX_LOG2N) return NTT_E_UNSUPPORTED;
         const uint64_t len = 1ull << n;
         if (d->offset[i] > (UINT64_MAX >> 3) - len) return NTT_E_ARG;
-        if (i > 0 && d->offset[i] < d->offset[i - 1] + (1ull << d->log2n[i - 1])) ascending = false;
+        if (i > 0) {
+            const uint64_t prev_end = d->offset[i - 1] + (1ull << d->log2n[i - 1]);
+            if (d->offset[i] < prev_end) ascending = false;
+            packed = packed && n == d->log2n[0] && d->offset[i] == prev_end;
+        }
         total = std::max(total, d->offset[i] + len);
     }
     if (!ascending) {
@@ -1038,6 +1059,24 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     const char* G = (const char*)g;
     char* H = (char*)h;
     hipStream_t s = (hipStream_t)stream;
+
+    // one length, items back to back: launched from the first offset and the
+    // count, with no per-length offset lists
+    if (packed && !(flags & (NTT_FLAG_PER_ITEM | NTT_FLAG_AUTOTUNE))) {
+        const uint32_t n = d->log2n[0];
+        const Plan* p = nullptr;
+        st = get_plan(m, n, powmod64(root % m, 1ull << (root_log2order - n), m), lnu, &p);
+        if (st != NTT_OK) return st;
+        BatchForm form;
+        uint8_t cf = CF_DEFAULT;
+        bool multi = false;   // a tuned form may run the one length in the multi-length kernel
+        if (lookup_form(shape_key_uniform(m, elem_bits, n, cnt), &form)) {
+            auto it = form.cls.find(n);
+            if (it != form.cls.end()) cf = it->second;
+            multi = form.multi && !(flags & NTT_FLAG_PER_CLASS) && n <= (uint32_t)multi_max_log2n((int)elem_bits);
+        }
+        if (!multi) return launch_items(n, cnt, d->offset[0], nullptr, p, elem_bits, F, G, H, s, stream, cf);
+    }
 
     // length classes
     std::map<uint32_t, std::vector<uint64_t>> cls;

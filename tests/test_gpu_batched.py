@@ -280,3 +280,29 @@ def test_release_stream_then_reuse(nt):
             nt.conv_batched(f, g, desc, M, out=out, stream=s)
         nt.release_stream(s)
         assert np.array_equal(host(out), ref), rep
+
+
+@pytest.mark.parametrize("n", [8, 12, 16])
+def test_packed_one_length_batch_from_an_offset(nt, n):
+    # one length, items back to back from a non-zero first offset (the packed
+    # launch path), plain and after NTT_FLAG_AUTOTUNE stored a form for the
+    # shape; the words before the first item stay untouched
+    count, first = 37, 3 << n
+    lengths = [n] * count
+    offs = [first + (i << n) for i in range(count)]
+    S = first + (count << n)
+    rng = np.random.default_rng(44 + n)
+    fh = rng.integers(0, M, S, dtype=np.uint32)
+    gh = rng.integers(0, M, S, dtype=np.uint32)
+    f, g = dev(fh), dev(gh)
+    desc = nt.BatchDesc(lengths, offs)
+    for flags in (0, nt.FLAG_AUTOTUNE, 0):
+        out = torch.full_like(f, 7)
+        o = host(nt.conv_batched(f, g, desc, M, out=out, flags=flags))
+        assert np.all(o[:first] == 7)
+        for k in (0, 17, count - 1):
+            a = offs[k]
+            idx = np.array([0, 1, (1 << n) - 1]) if n > 12 else np.arange(1 << n)
+            got = o[a:a + (1 << n)][idx]
+            want = oracle.conv_entries(fh[a:a + (1 << n)], gh[a:a + (1 << n)], M, idx).astype(got.dtype)
+            assert np.array_equal(got, want), (flags, k)
