@@ -66,6 +66,47 @@ def measured_traffic():
     return t["hbm_bytes_per_launch"]
 
 
+def write_traffic(prof_dir):
+    """Reduces the four rocprofv3 counter runs under prof_dir (FETCH_SIZE and
+    WRITE_SIZE of the headline bench, and of --calibrate-copy: directories
+    FETCH_SIZE, WRITE_SIZE, copy_FETCH_SIZE, copy_WRITE_SIZE) to HBM bytes per
+    launch of the fused kernel, each counter scaled by its reading for the
+    1 GiB copy, and writes the summary that measured_traffic() reads."""
+    import collections
+    import csv
+    import glob
+
+    def per_dispatch(sub, counter, kernel):
+        files = glob.glob(os.path.join(prof_dir, sub, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit("no counter_collection.csv under %s" % os.path.join(prof_dir, sub))
+        vals = collections.defaultdict(float)
+        with open(files[0]) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and kernel in r["Kernel_Name"]:
+                    vals[r.get("Dispatch_Id") or r.get("Correlation_Id")] += float(r["Counter_Value"])
+        if not vals:
+            raise SystemExit("no %s dispatches of %s in %s" % (counter, kernel, sub))
+        return sum(vals.values()) / len(vals)
+
+    fe = per_dispatch("FETCH_SIZE", "FETCH_SIZE", "k_conv_fused")
+    wr = per_dispatch("WRITE_SIZE", "WRITE_SIZE", "k_conv_fused")
+    cf = per_dispatch("copy_FETCH_SIZE", "FETCH_SIZE", "copy")
+    cw = per_dispatch("copy_WRITE_SIZE", "WRITE_SIZE", "copy")
+    copy_bytes = 1 << 30
+    ff, wf = copy_bytes / 1024 / cf, copy_bytes / 1024 / cw
+    out = {"kernel": "k_conv_fused<W32,16>", "workload": "batch4096_n65536_m13631489",
+           "source_sha": kernel_source_sha(),
+           "fetch_kb_per_launch": round(fe, 1), "write_kb_per_launch": round(wr, 1),
+           "copy_calibration": {"bytes": copy_bytes, "fetch_kb": round(cf, 1), "write_kb": round(cw, 1),
+                                "fetch_factor": ff, "write_factor": wf},
+           "hbm_bytes_per_launch": fe * 1024 * ff + wr * 1024 * wf}
+    path = os.path.join(ROOT, "profiles", "traffic_k_conv_fused_w32_n65536_b4096.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -108,7 +149,12 @@ def main():
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (reference kernel for the HBM byte counters)")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="only reduce the rocprofv3 FETCH_SIZE / WRITE_SIZE runs under DIR to the HBM-bytes summary "
+                         "in profiles/ (no GPU)")
     args = ap.parse_args()
+    if args.traffic_from:
+        return write_traffic(args.traffic_from)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(a batch would shard by items, one process per GPU); run with --gpus 1", file=sys.stderr)
