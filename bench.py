@@ -142,10 +142,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
-    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt", "conv2d", "u64"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt", "conv2d", "u64",
+                                           "lengths"], default="batch",
                     help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
                          "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
     ap.add_argument("--requests", type=int, default=4000, help="serve: timed requests")
+    ap.add_argument("--lengths", default="8,10,11,12,13,14,15,16,17,18,19",
+                    help="lengths: the log2 N of the uniform 2^26-element batches")
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (reference kernel for the HBM byte counters)")
@@ -173,6 +176,8 @@ def main():
         return serve_bench(args)
     if args.workload == "uneven":
         return uneven_bench(args)
+    if args.workload == "lengths":
+        return lengths_bench(args)
     if args.workload == "single":
         return single_bench(args)
     if args.workload in ("deconv", "euler", "crt", "conv2d", "u64"):
@@ -357,6 +362,38 @@ def uneven_bench(args):
                      "per_item_ms": float(per_item.mean()), "per_item_matches": same_item,
                      "per_item_conv_per_s": 10000 / (per_item.mean() / 1e3)}}
     print(json.dumps(out), flush=True)
+
+
+def lengths_bench(args):
+    """Per-length throughput of the default batch form: for each n, a batch of
+    2^26 elements (2^(26-n) convolutions of length 2^n, m = 13631489, items
+    back to back), one conv_batched call per step, in element-stages
+    (elements x log2 N) per second."""
+    import torch
+    import paper_1005_1497_amd as nt
+    import seeded_inputs as si
+    m = si.M_13631489
+    st = torch.cuda.current_stream()
+    res = {}
+    for n in [int(x) for x in args.lengths.split(",")]:
+        count = (1 << 26) >> n
+        tot = count << n
+        f = torch.from_numpy(si.uniform(100 + n, tot, m).view(np.int32)).cuda()
+        g = torch.from_numpy(si.uniform(200 + n, tot, m).view(np.int32)).cuda()
+        h = torch.empty_like(f)
+        desc = nt.BatchDesc([n] * count, si.offsets([n] * count))
+        run = lambda: nt.conv_batched(f, g, desc, m, out=h, stream=st)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        per = _time_ms(run, args.steps, st)
+        ms = float(per.mean())
+        res["n%d" % n] = {"items": count, "ms_per_batch": ms, "element_stages_per_s": tot * n / (ms / 1e3),
+                          "conv_per_s": count / (ms / 1e3)}
+        log("n=%d: %d items, %.3f ms" % (n, count, ms))
+        del f, g, h
+    print(json.dumps({"metric": "per-length batch throughput, 2^26 elements per batch", "unit": "element-stages/s",
+                      "config": {"workload": "lengths_2^26_elements_m13631489", "m": m}, "results": res}), flush=True)
 
 
 def single_bench(args):

@@ -306,3 +306,28 @@ def test_packed_one_length_batch_from_an_offset(nt, n):
             got = o[a:a + (1 << n)][idx]
             want = oracle.conv_entries(fh[a:a + (1 << n)], gh[a:a + (1 << n)], M, idx).astype(got.dtype)
             assert np.array_equal(got, want), (flags, k)
+
+
+@pytest.mark.parametrize("n,count", [(13, 180), (15, 350), (18, 180)])
+def test_fused_form_at_full_occupancy(nt, n, count):
+    # enough items to fill the resident workgroups, so the default form is the
+    # persistent fused kernel (fewer items take the four-step form); sampled
+    # outputs of the first, a middle and the last item against the oracle, and
+    # the whole output against the four-step form's
+    rng = np.random.default_rng(45 + n)
+    N = 1 << n
+    S = count * N
+    fh = rng.integers(0, M, S, dtype=np.uint32)
+    gh = rng.integers(0, M, S, dtype=np.uint32)
+    f, g = dev(fh), dev(gh)
+    desc = nt.BatchDesc([n] * count, si.offsets([n] * count))
+    o = host(nt.conv_batched(f, g, desc, M))
+    idx = np.concatenate([[0, 1, N - 1], rng.integers(0, N, 5)])
+    for k in (0, count // 2, count - 1):
+        a = k * N
+        assert np.array_equal(o[a:a + N][idx], oracle.conv_entries(fh[a:a + N], gh[a:a + N], M, idx).astype(o.dtype)), k
+    # two halves of the batch, each small enough for the four-step form
+    half = count // 3
+    d2 = nt.BatchDesc([n] * half, si.offsets([n] * half))
+    o2 = host(nt.conv_batched(f[:half * N], g[:half * N], d2, M))
+    assert np.array_equal(o2, o[:half * N])
