@@ -101,7 +101,22 @@ struct Blk {
     static constexpr int RL = (NP > 1) ? 16 : R0;      // radix of the last pass
     static constexpr int V0 = E / R0;                  // virtual items in pass 0
     static constexpr int VL = E / RL;                  // virtual items in the last pass
-    static constexpr int ROWP = (ORD == POS_FAST) ? (L + L / 16) : L;
+    // LDS rows of POS_FAST blocks.  Up to 256 positions a row is padded by
+    // one double per 16 (the two sequences of a 32-lane group then sit 272
+    // doubles apart).  From 512 on a sequence spans 32 lanes or more, and that
+    // padding wraps a 32-lane access of consecutive positions onto one bank
+    // twice; instead the low five bits of the position are XORed with bits
+    // 4..8 and with bits 5..7 (a permutation of every aligned 512 positions,
+    // no padding).  On 64 banks of 4 bytes, 32 lanes of 8-byte accesses per
+    // cycle, every exchange of the passes (the stride-R0 store after a
+    // radix-2/4/8 first pass included) and the reorder between forward and
+    // inverse then touch 32 distinct bank pairs per 32 lanes.  Applied to the
+    // 512-thread blocks (four-step rows, the multi-length kernel's tiles):
+    // measured 2% faster there.  The 256-thread product tiles keep the padding:
+    // with the swizzle their LDS instructions no longer pair up (28% more of
+    // them) and the tile of 1024 measured 30% slower.
+    static constexpr bool SWZ = (ORD == POS_FAST) && L >= 512 && S * L == 8192;
+    static constexpr int ROWP = (ORD == POS_FAST) ? (SWZ ? L : L + L / 16) : L;
     static constexpr int LDS_DOUBLES = (NP > 1) ? S * ROWP : 1;
     // every sequence's W work items are lanes of one wave (POS_FAST, W | 64):
     // its exchanges need no workgroup barrier
@@ -113,7 +128,8 @@ struct Blk {
     }
     __device__ static __forceinline__ int lds(int s, int pos) {
         if (ORD == SEQ_FAST) return pos * S + s;
-        return s * ROWP + pos + (pos >> 4);
+        if constexpr (SWZ) return s * ROWP + (pos ^ ((pos >> 4) & 31) ^ ((pos >> 5) & 7));
+        else return s * ROWP + pos + (pos >> 4);
     }
     // position of register i at the input of pass 0
     __device__ static __forceinline__ int pos0(int j, int i) {

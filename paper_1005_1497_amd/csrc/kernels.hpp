@@ -894,7 +894,7 @@ struct MultiCfg {
         if constexpr (N < 13) return 1;
         else return mx(FSLds<N>::WORDS, large_words<N - 1>());
     }
-    static constexpr int SMALL_WORDS = 8704;   // Blk<L, 8192/L, POS_FAST>::LDS_DOUBLES for 16 < L <= 4096
+    static constexpr int SMALL_WORDS = 8704;   // >= Blk<L, 8192/L, POS_FAST>::LDS_DOUBLES for 16 < L <= 4096
     static constexpr int WORDS = mx(large_words<NMAX>(), SMALL_WORDS);
 };
 
