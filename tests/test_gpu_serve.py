@@ -22,9 +22,12 @@ def test_served_equals_alone(bits, m):
     dt = np.uint64 if bits == 64 else np.uint32
     reqs = [(rng.integers(0, m, 1 << int(n), dtype=dt), rng.integers(0, m, 1 << int(n), dtype=dt)) for n in lens]
     ex = GpuExecutor(m, capacity_log2=21, elem_bits=bits, streams=2)
-    srv = ConvServer(ex, capacity_log2=21, max_inflight=4).start()
-    futs = []
-    for i, (f, g) in enumerate(reqs):
+    srv = ConvServer(ex, capacity_log2=21, max_inflight=4)
+    # the first 16 requests queue before the scheduler starts, so its first
+    # admission forms a batch of several whatever the timing of the box
+    futs = [srv.submit(f, g) for f, g in reqs[:16]]
+    srv.start()
+    for i, (f, g) in enumerate(reqs[16:]):
         futs.append(srv.submit(f, g))
         if i % 10 == 9:
             time.sleep(0.0005)      # arrivals while earlier batches run
@@ -74,7 +77,10 @@ def test_zero_copy_submission_and_result_lifetime():
 @pytest.mark.parametrize("bits,m", [(64, si.M_U64), (32, si.M_13631489)])
 def test_native_server_equals_alone(bits, m):
     # the library's own scheduler thread: every result equals the request run
-    # alone; two client threads submit at once; the oracle checks a few entries
+    # alone; two client threads submit at once; the oracle checks a few
+    # entries.  Operands are staged first and the threads only queue them, so
+    # the queue fills faster than a batch launches and batches form whatever
+    # the timing of the box.
     import threading
 
     import paper_1005_1497_amd as nt
@@ -83,11 +89,17 @@ def test_native_server_equals_alone(bits, m):
     lens = si.served_lengths(200, seed=6) if bits == 64 else rng.integers(4, 16, 200)
     dt = np.uint64 if bits == 64 else np.uint32
     reqs = [(rng.integers(0, m, 1 << int(n), dtype=dt), rng.integers(0, m, 1 << int(n), dtype=dt)) for n in lens]
-    tickets = [None] * len(reqs)
     with NativeConvServer(m, capacity_log2=21, elem_bits=bits, streams=4, max_batch_elems=1 << 19) as srv:
+        tickets = []
+        for f, g in reqs:
+            bf, bg, t = srv.stage(f.size)
+            bf[...] = f
+            bg[...] = g
+            tickets.append(t)
+
         def client(part):
             for i in range(part, len(reqs), 2):
-                tickets[i] = srv.submit(*reqs[i])
+                srv.submit_staged(tickets[i])
 
         ths = [threading.Thread(target=client, args=(k,)) for k in range(2)]
         for t in ths:

@@ -84,9 +84,12 @@ def _reqs(n, seed=0, lo=2, hi=8):
 
 def test_results_equal_alone_and_budget_respected():
     ex = FakeExecutor(M)
-    srv = ConvServer(ex, capacity_log2=10, min_log2=0, max_inflight=3).start()
+    srv = ConvServer(ex, capacity_log2=10, min_log2=0, max_inflight=3)
     reqs = _reqs(120, seed=1)
+    # queued before the scheduler starts: its first admissions form batches of
+    # several requests whatever the timing
     futs = [srv.submit(f, g) for f, g in reqs]
+    srv.start()
     srv.drain()
     srv.stop()
     for (f, g), fu in zip(reqs, futs):
