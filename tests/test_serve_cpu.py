@@ -104,9 +104,10 @@ def test_results_equal_alone_and_budget_respected():
 def test_admission_waits_for_memory():
     # capacity 2^8 elements: two 2^7 requests fill it; the third waits for a completion
     ex = FakeExecutor(M, delay=0.05)
-    srv = ConvServer(ex, capacity_log2=8, max_inflight=4).start()
+    srv = ConvServer(ex, capacity_log2=8, max_inflight=4)
     reqs = _reqs(3, seed=2, lo=7, hi=7)
-    futs = [srv.submit(f, g) for f, g in reqs]
+    futs = [srv.submit(f, g) for f, g in reqs]   # all queued before the first admission
+    srv.start()
     srv.drain()
     srv.stop()
     assert [len(b) for b in ex.launches][0] == 2
