@@ -583,8 +583,19 @@ ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan
 ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
                         std::map<uint32_t, const Plan*>& plans, uint32_t nmax, uint32_t elem_bits, const char* F,
                         const char* G, char* H, hipStream_t s, void* stream, bool transient = false) {
-    std::vector<uint64_t> toffs;
-    std::vector<uint64_t> tasks;   // two words per task: first item; log2n | count << 32
+    // the upload: item offsets (task order), then two words per task (first
+    // item; log2n | count << 32), then (transient) the plans; sized up front
+    size_t nitems = 0, ntask_words = 0;
+    for (auto& kv : cls) {
+        if (kv.first > nmax) continue;
+        const size_t tile = (int)kv.first <= SMALL_MAX_LOG2N ? (size_t)multi_tile((int)kv.first) : 1;
+        nitems += kv.second.size();
+        ntask_words += 2 * ((kv.second.size() + tile - 1) / tile);
+    }
+    std::vector<uint64_t> blob;
+    blob.reserve(nitems + ntask_words + 2 + (nmax + 1) * sizeof(DevPlan) / 8);
+    std::vector<uint64_t> tasks;
+    tasks.reserve(ntask_words);
     uint32_t nbig = 0;
     for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
         const uint32_t n = it->first;
@@ -592,16 +603,16 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
         const std::vector<uint64_t>& off = it->second;
         const uint32_t tile = (int)n <= SMALL_MAX_LOG2N ? (uint32_t)multi_tile((int)n) : 1u;
         if ((int)n > SMALL_MAX_LOG2N) nbig = std::max(nbig, n);
+        const size_t first = blob.size();   // the class's items follow in task order
         for (size_t i = 0; i < off.size(); i += tile) {
             const uint32_t k = (uint32_t)std::min<size_t>(tile, off.size() - i);
-            tasks.push_back(toffs.size());
+            tasks.push_back(first + i);
             tasks.push_back((uint64_t)n | ((uint64_t)k << 32));
-            toffs.insert(toffs.end(), off.begin() + i, off.begin() + i + k);
         }
+        blob.insert(blob.end(), off.begin(), off.end());
     }
     const uint32_t ntasks = (uint32_t)(tasks.size() / 2);
     if (ntasks == 0) return NTT_OK;
-    std::vector<uint64_t> blob(toffs);
     const size_t task_at = blob.size();
     blob.insert(blob.end(), tasks.begin(), tasks.end());
     // per-length plans, indexed by log2n
