@@ -69,6 +69,23 @@ struct Ring {
     int last = -1;   // slot handed out by the previous upload
 };
 
+// Key of the descriptor cache, (device, content), and a comparator that also
+// takes a view of a caller's vector, so that a lookup copies nothing.
+using OffKey = std::pair<int, std::vector<uint64_t>>;
+struct OffKeyView {
+    int dev;
+    const std::vector<uint64_t>* v;
+};
+struct OffKeyLess {
+    using is_transparent = void;
+    static bool lt(int da, const std::vector<uint64_t>& a, int db, const std::vector<uint64_t>& b) {
+        return da != db ? da < db : a < b;
+    }
+    bool operator()(const OffKey& a, const OffKey& b) const { return lt(a.first, a.second, b.first, b.second); }
+    bool operator()(const OffKey& a, const OffKeyView& b) const { return lt(a.first, a.second, b.dev, *b.v); }
+    bool operator()(const OffKeyView& a, const OffKey& b) const { return lt(a.dev, *a.v, b.first, b.second); }
+};
+
 struct Caches {
     std::mutex mu;
     std::map<std::tuple<int, uint64_t, int, uint64_t>, Plan> plans;   // (dev, m, log2n, root)
@@ -77,7 +94,7 @@ struct Caches {
     std::map<std::pair<int, void*>, Buf> queue;                       // (dev, stream) -> work queue
     std::map<std::pair<int, void*>, Buf> tune;                        // (dev, stream) -> autotuning output
     std::map<std::vector<uint64_t>, struct BatchForm> forms;          // batch shape -> tuned form
-    std::map<std::pair<int, std::vector<uint64_t>>, Buf> offsets;     // (dev, offsets) -> device copy
+    std::map<OffKey, Buf, OffKeyLess> offsets;                          // (dev, offsets) -> device copy
     std::map<std::pair<int, void*>, struct Ring> rings;               // (dev, stream) -> transient uploads
     std::vector<void*> retired;                                       // outgrown device buffers
     std::vector<void*> retired_host;                                  // outgrown pinned staging
@@ -319,8 +336,7 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, boo
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
     Caches& c = caches();
     std::lock_guard<std::mutex> g(c.mu);
-    auto key = std::make_pair(dev, h);
-    auto it = c.offsets.find(key);
+    auto it = c.offsets.find(OffKeyView{dev, &h});
     if (it == c.offsets.end()) {
         if (c.offsets.size() >= 256) {
             // evict what no captured graph references, after the device is idle
@@ -343,7 +359,7 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, boo
             return hip_status(e);
         }
         b.bytes = h.size() * sizeof(uint64_t);
-        it = c.offsets.emplace(key, b).first;
+        it = c.offsets.emplace(OffKey(dev, h), b).first;
     }
     if (keep) it->second.keep = true;
     *out = (const uint64_t*)it->second.ptr;
