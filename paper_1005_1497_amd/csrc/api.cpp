@@ -1152,9 +1152,20 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     // per length.
     const uint32_t nmax = (uint32_t)multi_max_log2n((int)elem_bits);
     size_t multi_classes = 0;
-    for (auto& kv : cls) multi_classes += kv.first <= nmax ? 1 : 0;
+    uint64_t multi_tasks = 0;
+    for (auto& kv : cls) {
+        if (kv.first > nmax) continue;
+        multi_classes += 1;
+        const uint64_t tile = (int)kv.first <= SMALL_MAX_LOG2N ? (uint64_t)multi_tile((int)kv.first) : 1;
+        multi_tasks += (kv.second.size() + tile - 1) / tile;
+    }
     BatchForm form;
-    form.multi = multi_classes >= 2;
+    // The single launch runs one task per workgroup; with fewer tasks than two
+    // thirds of its resident workgroups it would leave CUs idle, and each
+    // length's own launch (the four-step form for a few long items) spreads
+    // over the chip instead.
+    const uint64_t resident = (uint64_t)std::max(1, cu_count()) * std::max(1, multi_blocks_per_cu((int)elem_bits));
+    form.multi = multi_classes >= 2 && 3 * multi_tasks >= 2 * resident;
     const std::vector<uint64_t> key = shape_key(m, elem_bits, cls);
     if (!lookup_form(key, &form) && (flags & NTT_FLAG_AUTOTUNE)) {
         st = autotune(cls, plans, nmax, elem_bits, F, G, H, total, s, stream, &form);

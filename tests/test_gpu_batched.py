@@ -331,3 +331,26 @@ def test_fused_form_at_full_occupancy(nt, n, count):
     d2 = nt.BatchDesc([n] * half, si.offsets([n] * half))
     o2 = host(nt.conv_batched(f[:half * N], g[:half * N], d2, M))
     assert np.array_equal(o2, o[:half * N])
+
+
+def test_multi_length_launch_with_enough_tasks(nt):
+    # several lengths and more tasks than two thirds of the resident
+    # workgroups: the default form is the single multi-length launch (fewer
+    # tasks take one launch per length); against the per-length form and
+    # sampled oracle entries
+    rng = np.random.default_rng(46)
+    lengths = [int(x) for x in rng.integers(13, 17, 300)] + [int(x) for x in rng.integers(6, 13, 200)]
+    rng.shuffle(lengths)
+    offs = si.offsets(lengths)
+    S = int(offs[-1]) + (1 << lengths[-1])
+    fh = rng.integers(0, M, S, dtype=np.uint32)
+    gh = rng.integers(0, M, S, dtype=np.uint32)
+    f, g = dev(fh), dev(gh)
+    desc = nt.BatchDesc(lengths, offs)
+    o = host(nt.conv_batched(f, g, desc, M))
+    per_class = host(nt.conv_batched(f, g, desc, M, flags=nt.FLAG_PER_CLASS))
+    assert np.array_equal(o, per_class)
+    for k in (0, 123, 499):
+        a, N = int(offs[k]), 1 << lengths[k]
+        idx = np.array([0, 1, N - 1])
+        assert np.array_equal(o[a:a + N][idx], oracle.conv_entries(fh[a:a + N], gh[a:a + N], M, idx).astype(o.dtype)), k
