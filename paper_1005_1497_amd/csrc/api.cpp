@@ -1153,19 +1153,27 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
     const uint32_t nmax = (uint32_t)multi_max_log2n((int)elem_bits);
     size_t multi_classes = 0;
     uint64_t multi_tasks = 0;
+    bool long_contiguous = true;   // every length above the LDS kernels is one back-to-back run
     for (auto& kv : cls) {
         if (kv.first > nmax) continue;
         multi_classes += 1;
         const uint64_t tile = (int)kv.first <= SMALL_MAX_LOG2N ? (uint64_t)multi_tile((int)kv.first) : 1;
         multi_tasks += (kv.second.size() + tile - 1) / tile;
+        if ((int)kv.first > SMALL_MAX_LOG2N) {
+            const std::vector<uint64_t>& o = kv.second;
+            for (size_t i = 1; i < o.size() && long_contiguous; ++i)
+                long_contiguous = o[i] == o[0] + ((uint64_t)i << kv.first);
+        }
     }
     BatchForm form;
     // The single launch runs one task per workgroup; with fewer tasks than two
-    // thirds of its resident workgroups it would leave CUs idle, and each
-    // length's own launch (the four-step form for a few long items) spreads
-    // over the chip instead.
+    // thirds of its resident workgroups it would leave CUs idle.  Then, when
+    // every long length is one back-to-back run, each length's own launch
+    // (the four-step form for a few long items) spreads over the chip instead;
+    // scattered items (the four-step form needs a uniform stride) keep the
+    // single launch.
     const uint64_t resident = (uint64_t)std::max(1, cu_count()) * std::max(1, multi_blocks_per_cu((int)elem_bits));
-    form.multi = multi_classes >= 2 && 3 * multi_tasks >= 2 * resident;
+    form.multi = multi_classes >= 2 && (3 * multi_tasks >= 2 * resident || !long_contiguous);
     const std::vector<uint64_t> key = shape_key(m, elem_bits, cls);
     if (!lookup_form(key, &form) && (flags & NTT_FLAG_AUTOTUNE)) {
         st = autotune(cls, plans, nmax, elem_bits, F, G, H, total, s, stream, &form);
