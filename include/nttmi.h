@@ -73,7 +73,7 @@ typedef enum {
                                         powers of two, m, word width, device), and run
                                         it.  Synchronises the stream; not for use while
                                         the stream is being captured into a graph */
-#define NTT_FLAG_EULER         0x10u /* the Euler (Pollard) form of Sec. I, Eq. 4: any
+#define NTT_FLAG_EULER         0x10u /* the Euler (Pollard) form of Sec. I, Eq. 6: any
                                         prime m (not only those of which 2 is a
                                         lambda-root) with N | m - 1, and a root of exact
                                         order N that need not be a power of two
@@ -131,17 +131,26 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
  * (see ntt_batch_desc), all modulo the same m.  `root` has exact order
  * 2^root_log2order; item i uses root^(2^(root_log2order - log2n[i])), of
  * exact order N_i, so log2n[i] <= root_log2order is required.  The usual choice
- * is root = 2 and root_log2order = log2(ord_m(2)).  Default form: one fused
- * forward/pointwise/inverse persistent launch for every length up to 2^19
- * (32-bit words) or 2^18 (64-bit words), longer lengths one launch each; a
- * batch of a single length runs that length's own persistent kernel.  A form
- * tuned with NTT_FLAG_AUTOTUNE for the batch's shape replaces the default.
- * Every form gives the same result.  Once the call has run on a stream (its
- * plans, workspaces and any tuning in place) it is capturable into a HIP graph
- * on that stream.  The captured kernels keep that stream's workspace and work
- * queue: replay the graph on that stream, or ordered with every other use of
- * it.  A workspace that a later call outgrows is retired, not freed, so the
- * graph stays valid until ntt_release_caches. */
+ * is root = 2 and root_log2order = log2(ord_m(2)).  Default form:
+ *   - one length: lengths up to 2^12 run the LDS kernel (several items per
+ *     workgroup); longer lengths run the persistent fused kernel (one item per
+ *     workgroup at a time, from a per-stream work queue), except that a batch
+ *     whose items are back to back and number fewer than two thirds of that
+ *     kernel's resident workgroups runs the multi-launch four-step form,
+ *     whose phases spread every item over the chip;
+ *   - several lengths: one persistent launch covers every length up to 2^19
+ *     (32-bit words) or 2^18 (64-bit words), except that a batch with fewer
+ *     tasks than two thirds of that kernel's resident workgroups, whose items
+ *     of each length above 2^12 lie back to back, runs one launch per length
+ *     (each as above); longer lengths run one launch per length.
+ * A form tuned with NTT_FLAG_AUTOTUNE for the batch's shape replaces the
+ * default.  Every form gives the same result.  A call is capturable into a
+ * HIP graph on a stream once a call with the same batch shape (lengths, item
+ * counts, layout) has run on that stream: its plans, workspaces, work queue
+ * and any tuning are then in place.  The captured kernels keep that stream's
+ * workspace and work queue: replay the graph on that stream, or ordered with
+ * every other use of it.  A workspace that a later call outgrows is retired,
+ * not freed, so the graph stays valid until ntt_release_caches. */
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc *d, const void *f, const void *g, void *h,
                         uint32_t flags, void *stream);
@@ -155,8 +164,9 @@ ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint
  * Same requirements on m, N and root as conv_circular (NTT_FLAG_EULER
  * applies).  Returns NTT_E_SINGULAR when some forward(f) coefficient of some
  * row is zero (g is then unspecified).  Synchronises the stream (it reads the
- * singular flag back), so it is not for use while the stream is being captured.
- * g may equal h (in place); partial overlap is NTT_E_ARG. */
+ * singular flag back), so it is refused (NTT_E_UNSUPPORTED, nothing enqueued)
+ * while the stream is being captured.  g may equal h (in place); partial
+ * overlap is NTT_E_ARG. */
 ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
                            const void *f, const void *h, void *g, uint32_t batch,
                            uint32_t flags, void *stream);
@@ -277,6 +287,25 @@ ntt_status ntt_server_stats(ntt_server *srv, uint64_t *completed, double *mean_b
  * server may run concurrently with it or follow it.  The other ntt_server_*
  * calls are safe from several threads at once. */
 void ntt_server_destroy(ntt_server *srv);
+
+/* Diagnostics: cumulative counts, since the library was loaded (all devices
+ * and threads), of the launches it has made by form and of its descriptor
+ * uploads.  Writes counts[k] for k < min(n, NTT_COUNT_SLOTS); counts is a
+ * host array owned by the caller.  Lets a caller (the tests) see which form
+ * a call actually took: read before and after the call and compare. */
+enum {
+    NTT_COUNT_SMALL = 0,         /* LDS convolution kernels (N <= 2^12) */
+    NTT_COUNT_FOURSTEP = 1,      /* multi-launch four-step convolutions (one per launch sequence) */
+    NTT_COUNT_FUSED = 2,         /* persistent fused kernels of one length */
+    NTT_COUNT_MULTI = 3,         /* persistent launches over several lengths */
+    NTT_COUNT_TRANSFORM = 4,     /* transform launch sequences (ntt_forward / ntt_inverse rows) */
+    NTT_COUNT_DESC_CACHED = 5,   /* descriptors uploaded into the content-addressed cache */
+    NTT_COUNT_DESC_RING = 6,     /* descriptors uploaded through a stream's staging ring */
+    NTT_COUNT_DESC_EVICTED = 7,  /* cache entries freed when the cache was full */
+    NTT_COUNT_QUEUE_CREATED = 8, /* per-stream work queues created */
+    NTT_COUNT_SLOTS = 9
+};
+void ntt_launch_counts(uint64_t *counts, uint32_t n);
 
 /* Static description of a status code. */
 const char *ntt_status_string(ntt_status s);

@@ -59,6 +59,10 @@ def _load():
             lib.oracle_ntt.restype = INT
             lib.oracle_ntt_bins.argtypes = [_u64p, U64, U64, U64, _u64p, U64, _u64p]
             lib.oracle_ntt_bins.restype = INT
+            lib.oracle_ntt_bins_rows.argtypes = [_u64p, U64, U64, U64, U64, _u64p, U64, _u64p]
+            lib.oracle_ntt_bins_rows.restype = INT
+            lib.oracle_ntt2d_bins.argtypes = [_u64p, U64, U64, U64, U64, U64, _u64p, _u64p, U64, _u64p]
+            lib.oracle_ntt2d_bins.restype = INT
             lib.oracle_conv_direct.argtypes = [_u64p, _u64p, _u64p, U64, U64]
             lib.oracle_conv_entries.argtypes = [_u64p, _u64p, U64, U64, _u64p, U64, _u64p]
             lib.oracle_conv_via_ntt.argtypes = [_u64p, _u64p, _u64p, U64, U64, U64]
@@ -129,6 +133,38 @@ def ntt_bins(x, m: int, root: int, bins) -> np.ndarray:
     b = _arr(bins)
     out = np.zeros(b.size, dtype=np.uint64)
     _load().oracle_ntt_bins(_p(a), a.size, int(m), int(root), _p(b), b.size, _p(out))
+    return out
+
+
+def ntt_bins_rows(x, m: int, root: int, bins) -> np.ndarray:
+    """x: rows x N array; bins: rows x nbins array.  Returns X_r(bins[r, i])
+    of Eq. 2 for every row r (same root), each an O(N) sum."""
+    a = np.asarray(x)
+    b = np.asarray(bins)
+    if a.ndim != 2 or b.ndim != 2 or b.shape[0] != a.shape[0]:
+        raise ValueError("x must be rows x N and bins rows x nbins")
+    rows, N = a.shape
+    flat, fb = _arr(a.ravel()), _arr(b.ravel())
+    out = np.zeros(fb.size, dtype=np.uint64)
+    _load().oracle_ntt_bins_rows(_p(flat), rows, N, int(m), int(root), _p(fb), b.shape[1], _p(out))
+    return out.reshape(b.shape)
+
+
+def ntt2d_bins(x, m: int, root_r: int, root_c: int, bu, bv) -> np.ndarray:
+    """Selected outputs X(bu[i], bv[i]) of the 2-D transform of an R x C array
+    (Eq. 2 along each dimension), each the O(R C) double sum."""
+    a = np.asarray(x)
+    if a.ndim != 2:
+        raise ValueError("x must be 2-D")
+    R, C = a.shape
+    u, v = _arr(bu), _arr(bv)
+    if u.size != v.size:
+        raise ValueError("bu and bv must have the same length")
+    out = np.zeros(u.size, dtype=np.uint64)
+    rc = _load().oracle_ntt2d_bins(_p(_arr(a.ravel())), R, C, int(m), int(root_r), int(root_c), _p(u), _p(v),
+                                   u.size, _p(out))
+    if rc:
+        raise ValueError("oracle_ntt2d_bins failed with code %d" % rc)
     return out
 
 

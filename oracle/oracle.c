@@ -151,6 +151,64 @@ int oracle_ntt_bins(const uint64_t *x, uint64_t N, uint64_t m, uint64_t root,
     return 0;
 }
 
+/* Selected outputs of the forward transform of Eq. 2 for each of `rows`
+ * contiguous length-N sequences: out[r * nbins + i] = X_r(bins[r * nbins + i]),
+ * each the O(N) sum of oracle_ntt_bins (the same root for every row). */
+int oracle_ntt_bins_rows(const uint64_t *x, uint64_t rows, uint64_t N, uint64_t m, uint64_t root,
+                         const uint64_t *bins, uint64_t nbins, uint64_t *out) {
+    long long total = (long long)(rows * nbins);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long long q = 0; q < total; ++q) {
+        const uint64_t r = (uint64_t)q / nbins;
+        const uint64_t *xr = x + r * N;
+        uint64_t u = bins[q] % (N ? N : 1), z = 1 % m;
+        for (uint64_t k = 0; k < u; ++k) z = mulmod(z, root, m);
+        u128 acc = 0;
+        uint64_t zt = 1 % m;
+        for (uint64_t t = 0; t < N; ++t) {
+            acc += (u128)mulmod(xr[t], zt, m);
+            zt = mulmod(zt, z, m);
+        }
+        out[q] = (uint64_t)(acc % m);
+    }
+    return 0;
+}
+
+/* Selected outputs of the two-dimensional transform of an R x C array
+ * (row-major): Eq. 2 applied along each dimension with its own root,
+ *     X(u, v) = < sum_{k<R} sum_{l<C} x(k, l) root_r^(u k) root_c^(v l) >_m,
+ * out[i] = X(bu[i], bv[i]), each the O(R C) double sum (inner sum over l). */
+int oracle_ntt2d_bins(const uint64_t *x, uint64_t R, uint64_t C, uint64_t m, uint64_t root_r,
+                      uint64_t root_c, const uint64_t *bu, const uint64_t *bv, uint64_t nbins, uint64_t *out) {
+    for (uint64_t i = 0; i < nbins; ++i) {
+        uint64_t u = bu[i] % (R ? R : 1), v = bv[i] % (C ? C : 1);
+        uint64_t zr = 1 % m, zc = 1 % m;
+        for (uint64_t k = 0; k < u; ++k) zr = mulmod(zr, root_r, m);
+        for (uint64_t k = 0; k < v; ++k) zc = mulmod(zc, root_c, m);
+        /* zc^l for l < C, and the row sums S_k = sum_l x(k, l) zc^l */
+        uint64_t *pc = (uint64_t *)malloc((size_t)(C ? C : 1) * sizeof(uint64_t));
+        uint64_t *S = (uint64_t *)malloc((size_t)(R ? R : 1) * sizeof(uint64_t));
+        if (!pc || !S) { free(pc); free(S); return 3; }
+        oracle_powers(zc, m, C, pc);
+        long long rr = (long long)R;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (long long k = 0; k < rr; ++k) {
+            u128 acc = 0;
+            for (uint64_t l = 0; l < C; ++l) acc += (u128)mulmod(x[(uint64_t)k * C + l], pc[l], m);
+            S[k] = (uint64_t)(acc % m);
+        }
+        u128 acc = 0;
+        uint64_t zk = 1 % m;
+        for (uint64_t k = 0; k < R; ++k) {
+            acc += (u128)mulmod(S[k], zk, m);
+            zk = mulmod(zk, zr, m);
+        }
+        out[i] = (uint64_t)(acc % m);
+        free(pc); free(S);
+    }
+    return 0;
+}
+
 /* Circular convolution of Eq. 1, the O(N^2) direct sum:
  *     h(j) = < sum_{k<N} f(k) * g((j - k) mod N) >_m
  * (the index of g is read modulo N: the sequences are periodic, Sec. I). */
@@ -238,8 +296,10 @@ int oracle_conv_integer(const uint64_t *f, const uint64_t *g, uint64_t *h, uint6
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
     for (long long j = 0; j < n; ++j) {
         u128 acc = 0;
+        /* k = 0..N-1 in order; (j - k) mod N is j - k for k <= j and
+         * j + N - k above (no division in the inner loop) */
         for (uint64_t k = 0; k < N; ++k) {
-            uint64_t idx = ((uint64_t)j + N - k) % N;
+            uint64_t idx = k <= (uint64_t)j ? (uint64_t)j - k : (uint64_t)j + N - k;
             u128 p = (u128)f[k] * g[idx];
             if (acc + p < acc) bad = 1;
             acc += p;

@@ -25,7 +25,7 @@ __all__ = [
     "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt", "conv2d",
     "default_root", "modulus_order", "release_caches", "status_string",
     "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "FLAG_TRANSIENT", "STATUS",
-    "euler_root", "max_log2n", "copy_batch",
+    "euler_root", "max_log2n", "copy_batch", "launch_counts",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,7 +47,7 @@ EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_
            "conv2d_circular",
            "ntt_default_root",
            "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches",
-           "ntt_release_stream")
+           "ntt_release_stream", "ntt_launch_counts")
 
 
 class NttError(RuntimeError):
@@ -117,6 +117,8 @@ def _load():
     L.ntt_release_caches.restype = None
     L.ntt_release_stream.argtypes = [VP]
     L.ntt_release_stream.restype = None
+    L.ntt_launch_counts.argtypes = [ctypes.POINTER(U64), U32]
+    L.ntt_launch_counts.restype = None
     return L
 
 
@@ -303,10 +305,23 @@ class BatchDesc:
 
     def __init__(self, log2n, offsets):
         import numpy as np
-        self.log2n = np.ascontiguousarray(np.asarray(log2n, dtype=np.uint8))
-        self.offset = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        n = np.asarray(log2n)
+        if n.size and (n.min() < 0 or n.max() > 255):
+            raise ValueError("log2n values must lie in [0, 255]")
+        o = np.asarray(offsets)
+        if o.size and o.dtype.kind == "i" and o.min() < 0:
+            raise ValueError("offsets must be non-negative")
+        self.log2n = np.ascontiguousarray(n.astype(np.uint8))
+        self.offset = np.ascontiguousarray(o.astype(np.uint64))
         if self.log2n.shape != self.offset.shape:
             raise ValueError("log2n and offsets must have the same length")
+        # one past the last element any item touches (the C ABI is not given
+        # the buffer sizes, so the wrapper checks them against this)
+        if self.log2n.size and int(self.log2n.max()) < 64:
+            ends = self.offset + np.left_shift(np.uint64(1), self.log2n.astype(np.uint64))
+            self.extent = int(ends.max()) if int(ends.min()) >= int(self.offset.min()) else 1 << 64
+        else:
+            self.extent = 0 if not self.log2n.size else 1 << 64
         self.c = _BatchDesc(len(self.log2n),
                             self.log2n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                             self.offset.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
@@ -343,10 +358,25 @@ def conv_batched(f: torch.Tensor, g: torch.Tensor, desc, m: int, root: int = 2, 
         out = torch.empty_like(f)
     elif _words(out, "out") != bits or out.shape != f.shape:
         raise ValueError("out must match f")
+    if desc.extent > f.numel():
+        raise ValueError("the batch reaches element %d, beyond the %d elements of f, g and out"
+                         % (desc.extent, f.numel()))
     _check(lib.conv_batched(int(m), int(root), int(root_log2order), bits, ctypes.byref(desc.c),
                             ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()),
                             ctypes.c_void_p(out.data_ptr()), int(flags), _stream(stream)), "conv_batched")
     return out
+
+
+COUNT_NAMES = ("small", "fourstep", "fused", "multi", "transform", "desc_cached", "desc_ring", "desc_evicted",
+               "queue_created")
+
+
+def launch_counts() -> dict:
+    """Cumulative launch and descriptor-upload counts of the library by form
+    (diagnostics: read before and after a call to see which form it took)."""
+    buf = (ctypes.c_uint64 * len(COUNT_NAMES))()
+    lib.ntt_launch_counts(buf, len(COUNT_NAMES))
+    return dict(zip(COUNT_NAMES, (int(v) for v in buf)))
 
 
 def release_caches() -> None:

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -31,7 +32,12 @@ struct Buf {
     void* ptr = nullptr;
     size_t bytes = 0;
     bool keep = false;   // descriptor cache: referenced by a captured graph, never evicted
+    uint32_t pins = 0;   // descriptor cache: looked up by calls whose kernels are not yet enqueued
 };
+
+// Cumulative launch and upload counts by form (ntt_launch_counts).
+std::atomic<uint64_t> g_counts[NTT_COUNT_SLOTS];
+inline void count(int k, uint64_t by = 1) { g_counts[k].fetch_add(by, std::memory_order_relaxed); }
 
 // How conv_batched runs a batch: one persistent launch for the lengths it
 // covers (multi) or one launch per length, and the form of each length's
@@ -113,27 +119,10 @@ ntt_status hip_status(hipError_t e) {
     return NTT_E_DEVICE;
 }
 
-ModC make_modc(uint64_t m) {
-    ModC M;
-    M.m = (double)m;
-    M.minv = 1.0 / (double)m;
-    M.C = 6755399441055744.0;  // 1.5 * 2^52
-    M.Cm = M.C * (double)m;    // exact for m < 2^26 (3m fits the significand)
-    M.c32 = (double)((1ull << 32) % m);
-    return M;
-}
-
-double2 tw_pair(uint64_t w, uint64_t m) {
-    double2 t;
-    t.x = (double)w;
-    t.y = (double)w / (double)m;
-    return t;
-}
-
 // (log2 nu, v2) of a modulus: log2 of the order of 2 when m is prime and that
 // order is a power of two (2 is a lambda-root of m: Sec. II, Prop. 2), and the
 // 2-adic valuation of m - 1 when m is prime (the longest power-of-two length
-// of the Euler form, Sec. I, Eq. 4); -1 where they do not apply.  Cached.
+// of the Euler form, Sec. I, Eq. 6); -1 where they do not apply.  Cached.
 std::pair<int, int> modulus_info(uint64_t m) {
     Caches& c = caches();
     {
@@ -325,13 +314,32 @@ ntt_status get_queue(void* stream, uint32_t** out) {
             return hip_status(e);
         }
         b.bytes = 256;
+        count(NTT_COUNT_QUEUE_CREATED);
     }
     *out = (uint32_t*)b.ptr;
     return NTT_OK;
 }
 
-// Device copy of an offsets array, cached by content (uploaded once).
-ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, bool keep = false) {
+// A descriptor in device memory for one call.  When it comes from the
+// content-addressed cache it stays pinned there, so that no eviction frees it,
+// until the call has enqueued the kernel that reads it (end of scope).
+using OffMap = std::map<OffKey, Buf, OffKeyLess>;
+struct DescRef {
+    const uint64_t* ptr = nullptr;
+    bool pinned = false;
+    OffMap::iterator it;
+    DescRef() = default;
+    DescRef(const DescRef&) = delete;
+    DescRef& operator=(const DescRef&) = delete;
+    ~DescRef();
+};
+
+// Device copy of an offsets array, cached by content (uploaded once) and
+// pinned in `ref` for the caller.  A full cache (256 entries) first waits for
+// the device and frees every entry that no call holds pinned and no captured
+// graph references: kernels enqueued earlier have then run, and descriptors
+// looked up but not yet launched (by this or another thread) are pinned.
+ntt_status get_offsets(const std::vector<uint64_t>& h, DescRef* ref, bool keep = false) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
     Caches& c = caches();
@@ -339,14 +347,14 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, boo
     auto it = c.offsets.find(OffKeyView{dev, &h});
     if (it == c.offsets.end()) {
         if (c.offsets.size() >= 256) {
-            // evict what no captured graph references, after the device is idle
             (void)hipDeviceSynchronize();
             for (auto e = c.offsets.begin(); e != c.offsets.end();) {
-                if (e->second.keep) {
+                if (e->second.keep || e->second.pins) {
                     ++e;
                 } else {
                     (void)hipFree(e->second.ptr);
                     e = c.offsets.erase(e);
+                    count(NTT_COUNT_DESC_EVICTED);
                 }
             }
         }
@@ -360,10 +368,20 @@ ntt_status get_offsets(const std::vector<uint64_t>& h, const uint64_t** out, boo
         }
         b.bytes = h.size() * sizeof(uint64_t);
         it = c.offsets.emplace(OffKey(dev, h), b).first;
+        count(NTT_COUNT_DESC_CACHED);
     }
     if (keep) it->second.keep = true;
-    *out = (const uint64_t*)it->second.ptr;
+    it->second.pins += 1;
+    ref->ptr = (const uint64_t*)it->second.ptr;
+    ref->pinned = true;
+    ref->it = it;
     return NTT_OK;
+}
+
+DescRef::~DescRef() {
+    if (!pinned) return;
+    std::lock_guard<std::mutex> g(caches().mu);
+    it->second.pins -= 1;
 }
 
 // Device copy of a descriptor used by one call: through the stream's staging
@@ -377,7 +395,7 @@ ntt_status stream_capturing(void* stream, bool* capturing) {
     return NTT_OK;
 }
 
-ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream, const uint64_t** out) {
+ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream, DescRef* out) {
     bool capturing = false;
     if (stream_capturing(stream, &capturing) != NTT_OK) return NTT_E_DEVICE;
     if (!transient || capturing) return get_offsets(h, out, capturing);
@@ -431,7 +449,8 @@ ntt_status get_desc(const std::vector<uint64_t>& h, bool transient, void* stream
     std::memcpy(sl.host, h.data(), h.size() * sizeof(uint64_t));
     e = hipMemcpyAsync(sl.dev, sl.host, h.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_status(e);
-    *out = (const uint64_t*)sl.dev;
+    out->ptr = (const uint64_t*)sl.dev;
+    count(NTT_COUNT_DESC_RING);
     return NTT_OK;
 }
 
@@ -476,11 +495,14 @@ ntt_status check_range(uint32_t wbits, const void* x, uint64_t n, uint64_t m, vo
 ntt_status conv_one(const Plan* p, uint32_t wbits, uint32_t log2n, const void* f, const void* g, void* h,
                     void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if ((int)log2n <= SMALL_MAX_LOG2N)
+    if ((int)log2n <= SMALL_MAX_LOG2N) {
+        count(NTT_COUNT_SMALL);
         return hip_status(launch_conv_small((int)wbits, log2n, f, g, h, nullptr, 1, p->dev, s));
+    }
     void* ws = nullptr;
     ntt_status st = get_buf(caches().work, stream, ((size_t)2 * (wbits / 8)) << log2n, &ws);
     if (st != NTT_OK) return st;
+    count(NTT_COUNT_FOURSTEP);
     return hip_status(launch_conv_fourstep((int)wbits, log2n, f, g, h, 1, 0, ws, p->dev, s));
 }
 
@@ -489,6 +511,7 @@ ntt_status conv_one(const Plan* p, uint32_t wbits, uint32_t log2n, const void* f
 ntt_status ntt_rows(const Plan* p, uint32_t elem_bits, uint32_t log2n, bool inv, const void* x, void* X,
                     uint32_t batch, void* stream) {
     hipStream_t s = (hipStream_t)stream;
+    count(NTT_COUNT_TRANSFORM);
     if ((int)log2n <= SMALL_MAX_LOG2N)
         return hip_status(launch_ntt_small((int)elem_bits, log2n, inv, x, X, batch, p->dev, s));
     const size_t wb = elem_bits / 8;
@@ -535,9 +558,11 @@ ntt_status launch_items(uint32_t n, uint32_t c, uint64_t base, const uint64_t* d
     const size_t wb = elem_bits / 8;
     const bool contiguous = doffs == nullptr;
     ntt_status st = NTT_OK;
-    if ((int)n <= SMALL_MAX_LOG2N)
+    if ((int)n <= SMALL_MAX_LOG2N) {
+        count(NTT_COUNT_SMALL);
         return hip_status(launch_conv_small((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c,
                                             p->dev, s, form == CF_SMALL_WAVE ? SMALL_TILE_WAVE : SMALL_TILE_256));
+    }
     // multi-launch four-step form: every phase spreads all items over the
     // chip; scratch 2N words per item, within 1 GiB
     const bool fourstep_ok = contiguous && (((uint64_t)2 * c * wb) << n) <= (1ull << 30);
@@ -545,6 +570,7 @@ ntt_status launch_items(uint32_t n, uint32_t c, uint64_t base, const uint64_t* d
         void* ws = nullptr;
         const ntt_status e = get_buf(caches().work, stream, (size_t)(((uint64_t)2 * c * wb) << n), &ws);
         if (e != NTT_OK) return e;
+        count(NTT_COUNT_FOURSTEP);
         return hip_status(launch_conv_fourstep((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, c,
                                                1ull << n, ws, p->dev, s));
     };
@@ -572,6 +598,7 @@ ntt_status launch_items(uint32_t n, uint32_t c, uint64_t base, const uint64_t* d
     uint32_t* q = nullptr;
     st = get_queue(stream, &q);
     if (st != NTT_OK) return st;
+    count(NTT_COUNT_FUSED);
     return hip_status(launch_conv_fused((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, doffs, c,
                                         ws, q, (uint32_t)grid, p->dev, s));
 }
@@ -583,12 +610,12 @@ ntt_status launch_class(uint32_t n, const std::vector<uint64_t>& off, const Plan
     // contiguous uniform run: offsets base + i N, no table needed
     bool contiguous = true;
     for (uint32_t i = 1; i < c && contiguous; ++i) contiguous = off[i] == off[0] + ((uint64_t)i << n);
-    const uint64_t* doffs = nullptr;
+    DescRef doffs;   // pinned until the launch below is enqueued
     if (!contiguous) {
         const ntt_status st = get_desc(off, transient, stream, &doffs);
         if (st != NTT_OK) return st;
     }
-    return launch_items(n, c, contiguous ? off[0] : 0, doffs, p, elem_bits, F, G, H, s, stream, form);
+    return launch_items(n, c, contiguous ? off[0] : 0, doffs.ptr, p, elem_bits, F, G, H, s, stream, form);
 }
 
 // One persistent launch for every class of length <= 2^nmax.  The task list
@@ -639,25 +666,16 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
         if (kv.first <= nmax) hp[kv.first] = kv.second->dev;
     std::vector<uint64_t> pw(hp.size() * sizeof(DevPlan) / 8);
     std::memcpy(pw.data(), hp.data(), pw.size() * 8);
-    const uint64_t* dblob = nullptr;
-    const uint64_t* dplans = nullptr;
-    bool capturing = false;
-    ntt_status st = stream_capturing(stream, &capturing);
+    // one upload: items and tasks, padded to 16 bytes, then the plans (one
+    // descriptor, pinned until the launch is enqueued)
+    const size_t plans_at = (blob.size() + 1) & ~(size_t)1;
+    blob.resize(plans_at, 0);
+    blob.insert(blob.end(), pw.begin(), pw.end());
+    DescRef desc;
+    ntt_status st = get_desc(blob, transient, stream, &desc);
     if (st != NTT_OK) return st;
-    if (transient && !capturing) {
-        // one upload: items and tasks, padded to 16 bytes, then the plans
-        const size_t plans_at = (blob.size() + 1) & ~(size_t)1;
-        blob.resize(plans_at, 0);
-        blob.insert(blob.end(), pw.begin(), pw.end());
-        st = get_desc(blob, true, stream, &dblob);
-        if (st != NTT_OK) return st;
-        dplans = dblob + plans_at;
-    } else {
-        st = get_desc(blob, false, stream, &dblob);
-        if (st != NTT_OK) return st;
-        st = get_desc(pw, false, stream, &dplans);
-        if (st != NTT_OK) return st;
-    }
+    const uint64_t* dblob = desc.ptr;
+    const uint64_t* dplans = dblob + plans_at;
     const size_t wb = elem_bits / 8;
     const uint64_t scratch_words = nbig ? (2ull << nbig) : 1;
     uint64_t grid = (uint64_t)std::max(1, cu_count()) * std::max(1, multi_blocks_per_cu((int)elem_bits));
@@ -669,6 +687,7 @@ ntt_status launch_multi(const std::map<uint32_t, std::vector<uint64_t>>& cls,
     uint32_t* q = nullptr;
     st = get_queue(stream, &q);
     if (st != NTT_OK) return st;
+    count(NTT_COUNT_MULTI);
     return hip_status(launch_conv_multi((int)elem_bits, F, G, H, dblob + task_at, ntasks, dblob, ws, scratch_words, q,
                                         (uint32_t)grid, (const DevPlan*)(const void*)dplans, s));
 }
@@ -893,6 +912,12 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
     const size_t wb = elem_bits / 8;
     const size_t bytes = ((size_t)batch << log2n) * wb;
     if (overlap(f, bytes, g, bytes) == 2 || overlap(h, bytes, g, bytes) == 2) return NTT_E_ARG;
+    // the singular flag is read back with a synchronisation, which a stream
+    // being captured cannot do: refuse before anything is enqueued
+    bool capturing = false;
+    st = stream_capturing(stream, &capturing);
+    if (st != NTT_OK) return st;
+    if (capturing) return NTT_E_UNSUPPORTED;
     if (flags & NTT_FLAG_CHECK_RANGE) {
         st = check_range(elem_bits, f, (uint64_t)batch << log2n, m, stream);
         if (st == NTT_OK) st = check_range(elem_bits, h, (uint64_t)batch << log2n, m, stream);
@@ -911,6 +936,7 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
     const char* Hh = (const char*)h;
     char* Gg = (char*)g;
     if ((int)log2n <= SMALL_MAX_LOG2N) {
+        count(NTT_COUNT_SMALL);
         e = launch_conv_small((int)elem_bits, log2n, F, Hh, Gg, nullptr, batch, p->dev, s, SMALL_TILE_256,
                               (uint32_t*)flag);
     } else {
@@ -926,6 +952,7 @@ ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t e
         uint32_t* q = nullptr;
         st = get_queue(stream, &q);
         if (st != NTT_OK) return st;
+        count(NTT_COUNT_FUSED);
         e = launch_conv_fused((int)elem_bits, (int)log2n, F, Hh, Gg, nullptr, batch, ws, q, (uint32_t)grid, p->dev, s,
                               (uint32_t*)flag);
     }
@@ -985,6 +1012,7 @@ ntt_status conv_crt(uint32_t log2n, const void* f, const void* g, void* h, uint3
         st = get_queue(stream, &q);
         if (st != NTT_OK) return st;
         const CrtStore cs{a1, (uint64_t*)h, (uint32_t)m1, c};
+        count(NTT_COUNT_FUSED);
         return hip_status(launch_conv_fused(32, (int)log2n, f, g, nullptr, nullptr, batch, ws, q, (uint32_t)grid,
                                             p2->dev, s, nullptr, &cs));
     }
@@ -1256,6 +1284,11 @@ const char* ntt_status_string(ntt_status s) {
 }
 
 void ntt_release_stream(void* stream) { nttmi::release_stream_caches(stream); }
+
+void ntt_launch_counts(uint64_t* counts, uint32_t n) {
+    if (!counts) return;
+    for (uint32_t k = 0; k < n && k < (uint32_t)NTT_COUNT_SLOTS; ++k) counts[k] = g_counts[k].load(std::memory_order_relaxed);
+}
 
 void ntt_release_caches(void) {
     Caches& c = caches();

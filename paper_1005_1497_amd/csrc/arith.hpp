@@ -10,6 +10,9 @@
 // The quotient may be off by one only when b*w/m lies within ~1e-7 of a
 // half-integer, so the remainder stays within m/2 + 2 in every case.
 //
+// Every routine here is also compiled for the host, so that a CPU test can
+// sweep them against exact integer arithmetic.
+//
 // This is the word-level form of the paper's twiddle product (Eq. 2): the
 // coefficients are the powers 2^e mod m of the digital circle (Eq. 5) and the
 // reduction is the <.>_m of Appendix A; see the design notes for why literal
@@ -29,7 +32,26 @@ struct ModC {
     double c32;    // 2^32 mod m (64-bit words: reduction of the high half on load)
 };
 
-__device__ __forceinline__ double mulmod(double b, double w, double wq, const ModC& M) {
+// The constants of modulus m (host side; kernels receive them by value).
+inline ModC make_modc(uint64_t m) {
+    ModC M;
+    M.m = (double)m;
+    M.minv = 1.0 / (double)m;
+    M.C = 6755399441055744.0;  // 1.5 * 2^52
+    M.Cm = M.C * (double)m;    // exact for m < 2^26 (3m fits the significand)
+    M.c32 = (double)((1ull << 32) % m);
+    return M;
+}
+
+// A twiddle w as the pair (w, w/m) that mulmod takes (host side).
+inline double2 tw_pair(uint64_t w, uint64_t m) {
+    double2 t;
+    t.x = (double)w;
+    t.y = (double)w / (double)m;
+    return t;
+}
+
+__host__ __device__ __forceinline__ double mulmod(double b, double w, double wq, const ModC& M) {
     double q = __builtin_fma(b, wq, M.C);
     double x = __builtin_fma(q, -M.m, M.Cm);
     return __builtin_fma(b, w, x);
@@ -37,7 +59,7 @@ __device__ __forceinline__ double mulmod(double b, double w, double wq, const Mo
 
 // a*b mod m for two variable operands with |a*b| < 2^53 - m; result in
 // [-m/2 - 2, m/2 + 2].
-__device__ __forceinline__ double mulmod_var(double a, double b, const ModC& M) {
+__host__ __device__ __forceinline__ double mulmod_var(double a, double b, const ModC& M) {
     double bq = b * M.minv;
     double q = __builtin_fma(a, bq, M.C);
     double x = __builtin_fma(q, -M.m, M.Cm);
@@ -45,22 +67,22 @@ __device__ __forceinline__ double mulmod_var(double a, double b, const ModC& M) 
 }
 
 // y mod m into [-m/2 - 2, m/2 + 2] for |y| < 2^51.
-__device__ __forceinline__ double reduce(double y, const ModC& M) {
+__host__ __device__ __forceinline__ double reduce(double y, const ModC& M) {
     double q = __builtin_fma(y, M.minv, M.C);
     double x = __builtin_fma(q, -M.m, M.Cm);
     return y + x;
 }
 
 // Canonical residue in [0, m) (Appendix A) as an unsigned word.
-__device__ __forceinline__ uint32_t canon_u32(double y, const ModC& M) {
+__host__ __device__ __forceinline__ uint32_t canon_u32(double y, const ModC& M) {
     double r = reduce(y, M);
     r = (r < 0.0) ? r + M.m : r;
     return (uint32_t)r;
 }
 
 // Scratch words hold reduced residues as signed 32-bit integers.
-__device__ __forceinline__ int32_t to_i32(double y) { return (int32_t)y; }
-__device__ __forceinline__ double from_i32(int32_t v) { return (double)v; }
+__host__ __device__ __forceinline__ int32_t to_i32(double y) { return (int32_t)y; }
+__host__ __device__ __forceinline__ double from_i32(int32_t v) { return (double)v; }
 
 }  // namespace nttmi
 
@@ -87,19 +109,19 @@ struct W32 {
     using sword = int32_t;
     static constexpr int WB = 4;   // bytes per word
     static constexpr int SB = 4;   // bytes per scratch word
-    __device__ static __forceinline__ double mul_tw(double b, const double2& w, const ModC& M) {
+    __host__ __device__ static __forceinline__ double mul_tw(double b, const double2& w, const ModC& M) {
         return mulmod(b, w.x, w.y, M);
     }
-    __device__ static __forceinline__ double mul_w(double b, double w, const ModC& M) { return mulmod_var(b, w, M); }
-    __device__ static __forceinline__ double mul_var(double a, double b, const ModC& M) { return mulmod_var(a, b, M); }
-    __device__ static __forceinline__ double load_reduce(word x, const ModC& M) { return reduce((double)x, M); }
-    __device__ static __forceinline__ word canon(double y, const ModC& M) { return canon_u32(y, M); }
-    __device__ static __forceinline__ sword to_s(double y) { return (int32_t)y; }
-    __device__ static __forceinline__ double from_s(sword v) { return (double)v; }
-    __device__ static __forceinline__ double reduce_s(double y, const ModC& M) { return reduce(y, M); }
+    __host__ __device__ static __forceinline__ double mul_w(double b, double w, const ModC& M) { return mulmod_var(b, w, M); }
+    __host__ __device__ static __forceinline__ double mul_var(double a, double b, const ModC& M) { return mulmod_var(a, b, M); }
+    __host__ __device__ static __forceinline__ double load_reduce(word x, const ModC& M) { return reduce((double)x, M); }
+    __host__ __device__ static __forceinline__ word canon(double y, const ModC& M) { return canon_u32(y, M); }
+    __host__ __device__ static __forceinline__ sword to_s(double y) { return (int32_t)y; }
+    __host__ __device__ static __forceinline__ double from_s(sword v) { return (double)v; }
+    __host__ __device__ static __forceinline__ double reduce_s(double y, const ModC& M) { return reduce(y, M); }
 };
 
-__device__ __forceinline__ double mulmod_dd(double b, double w, const ModC& M) {
+__host__ __device__ __forceinline__ double mulmod_dd(double b, double w, const ModC& M) {
     const double hi = b * w;
     const double lo = __builtin_fma(b, w, -hi);
     const double q = __builtin_fma(hi, M.minv, M.C) - M.C;
@@ -108,7 +130,7 @@ __device__ __forceinline__ double mulmod_dd(double b, double w, const ModC& M) {
 }
 
 // y mod m into about [-m/2, m/2] for |y| < 2^52 (64-bit words).
-__device__ __forceinline__ double reduce_dd(double y, const ModC& M) {
+__host__ __device__ __forceinline__ double reduce_dd(double y, const ModC& M) {
     const double q = __builtin_fma(y, M.minv, M.C) - M.C;
     return __builtin_fma(q, -M.m, y);
 }
@@ -118,17 +140,17 @@ struct W64 {
     using sword = double;
     static constexpr int WB = 8;
     static constexpr int SB = 8;
-    __device__ static __forceinline__ double mul_tw(double b, const double2& w, const ModC& M) {
+    __host__ __device__ static __forceinline__ double mul_tw(double b, const double2& w, const ModC& M) {
         return mulmod_dd(b, w.x, M);
     }
-    __device__ static __forceinline__ double mul_w(double b, double w, const ModC& M) { return mulmod_dd(b, w, M); }
-    __device__ static __forceinline__ double mul_var(double a, double b, const ModC& M) { return mulmod_dd(a, b, M); }
+    __host__ __device__ static __forceinline__ double mul_w(double b, double w, const ModC& M) { return mulmod_dd(b, w, M); }
+    __host__ __device__ static __forceinline__ double mul_var(double a, double b, const ModC& M) { return mulmod_dd(a, b, M); }
     // x = xh 2^32 + xl; (xh * (2^32 mod m) mod m) + xl, then reduced
-    __device__ static __forceinline__ double load_reduce(word x, const ModC& M) {
+    __host__ __device__ static __forceinline__ double load_reduce(word x, const ModC& M) {
         const double h = mulmod_dd((double)(uint32_t)(x >> 32), M.c32, M);
         return reduce_dd(h + (double)(uint32_t)x, M);
     }
-    __device__ static __forceinline__ word canon(double y, const ModC& M) {
+    __host__ __device__ static __forceinline__ word canon(double y, const ModC& M) {
         double r = reduce_dd(y, M);
         r = (r < 0.0) ? r + M.m : r;
         r = (r >= M.m) ? r - M.m : r;
@@ -136,9 +158,9 @@ struct W64 {
         const double lo = __builtin_fma(hi, -4294967296.0, r);
         return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
     }
-    __device__ static __forceinline__ sword to_s(double y) { return y; }
-    __device__ static __forceinline__ double from_s(sword v) { return v; }
-    __device__ static __forceinline__ double reduce_s(double y, const ModC& M) { return reduce_dd(y, M); }
+    __host__ __device__ static __forceinline__ sword to_s(double y) { return y; }
+    __host__ __device__ static __forceinline__ double from_s(sword v) { return v; }
+    __host__ __device__ static __forceinline__ double reduce_s(double y, const ModC& M) { return reduce_dd(y, M); }
 };
 
 // x^e mod m by left-to-right square and multiply over the bits of e (bit
@@ -146,7 +168,7 @@ struct W64 {
 // branch is too).  x reduced; result reduced.  With e = m - 2 this is the
 // inverse of x for a prime m (Fermat's little theorem), 0 for x = 0.
 template <class W>
-__device__ __forceinline__ double pow_mod(double x, uint64_t e, int top, const ModC& M) {
+__host__ __device__ __forceinline__ double pow_mod(double x, uint64_t e, int top, const ModC& M) {
     double r = x;
     for (int b = top - 1; b >= 0; --b) {
         r = W::mul_var(r, r, M);

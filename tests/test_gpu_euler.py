@@ -1,4 +1,4 @@
-"""GPU parity of the Euler (Pollard) form of Sec. I, Eq. 4 (NTT_FLAG_EULER):
+"""GPU parity of the Euler (Pollard) form of Sec. I, Eq. 6 (NTT_FLAG_EULER):
 primes k*2^n + 1 of which 2 is not a lambda-root, roots of unity that are not
 powers of two, and lengths beyond the order of 2 for a Rader prime.  Every
 result is compared bit for bit with the oracle (whose root is passed in)."""

@@ -307,7 +307,7 @@ def test_worked_example_f17():
 
 
 # ---------------------------------------------------------------- Euler form
-# Sec. I, Eq. 4 (Pollard's form by Euler's theorem): primes k*2^n + 1 whose
+# Sec. I, Eq. 6 (Pollard's form by Euler's theorem): primes k*2^n + 1 whose
 # roots of unity are not powers of two.  The root below is built here with
 # Python integers (the smallest quadratic non-residue z, raised to (p-1)/N), and
 # its order is checked against the definition before the oracle is trusted.
@@ -473,3 +473,61 @@ def test_conv2d_reduces_to_1d_and_separates():
     assert np.array_equal(lhs, outer(oracle.conv_direct(p, r, m), oracle.conv_direct(q, s, m)))
     idx = np.array([0, 5, 31], np.uint64)
     assert np.array_equal(oracle.conv2d_entries(outer(p, q), outer(r, s), m, idx), lhs.ravel()[idx.astype(int)])
+
+
+# ---------------------------------------------------------------- batched and 2-D bins
+def test_ntt_bins_rows_match_single_rows_and_deltas():
+    # every row's bins equal ntt_bins of that row (pinned above against the full
+    # O(N^2) transform); a delta at s gives X(u) = root^(u s) (Eq. 2)
+    m, nu, N, rows = 13631489, 1 << 19, 256, 5
+    w = root_of_order(m, nu, N, odd=3)
+    rng = np.random.default_rng(8)
+    x = rng.integers(0, m, (rows, N), dtype=np.uint64)
+    bins = rng.integers(0, N, (rows, 4)).astype(np.uint64)
+    got = oracle.ntt_bins_rows(x, m, w, bins)
+    for r in range(rows):
+        assert got[r].tolist() == oracle.ntt_bins(x[r], m, w, bins[r]).tolist()
+    d = np.zeros((rows, N), np.uint64)
+    for r in range(rows):
+        d[r, 7 * r + 1] = 1
+    got = oracle.ntt_bins_rows(d, m, w, bins)
+    for r in range(rows):
+        assert got[r].tolist() == [pow(w, int(u) * (7 * r + 1), m) for u in bins[r]]
+
+
+def test_ntt2d_bins_closed_forms():
+    m, nu = 13631489, 1 << 19
+    R, C = 8, 16
+    wr, wc = root_of_order(m, nu, R), root_of_order(m, nu, C, odd=5)
+    rng = np.random.default_rng(9)
+    bu = rng.integers(0, R, 12).astype(np.uint64)
+    bv = rng.integers(0, C, 12).astype(np.uint64)
+    # a delta at (k0, l0): X(u, v) = wr^(u k0) wc^(v l0)
+    d = np.zeros((R, C), np.uint64)
+    d[3, 11] = 1
+    assert oracle.ntt2d_bins(d, m, wr, wc, bu, bv).tolist() == \
+        [pow(wr, 3 * int(u), m) * pow(wc, 11 * int(v), m) % m for u, v in zip(bu, bv)]
+    # separable: outer(a, b) -> A(u) B(v), with the 1-D transforms of Eq. 2
+    a = rng.integers(0, m, R, dtype=np.uint64)
+    b = rng.integers(0, m, C, dtype=np.uint64)
+    outer = np.array([[int(p) * int(q) % m for q in b] for p in a], dtype=np.uint64)
+    A, B = oracle.ntt(a, m, wr), oracle.ntt(b, m, wc)
+    assert oracle.ntt2d_bins(outer, m, wr, wc, bu, bv).tolist() == \
+        [int(A[int(u)]) * int(B[int(v)]) % m for u, v in zip(bu, bv)]
+    # the 2-D convolution theorem against the direct 2-D sum
+    f = rng.integers(0, m, (R, C), dtype=np.uint64)
+    g = rng.integers(0, m, (R, C), dtype=np.uint64)
+    h = oracle.conv2d_direct(f, g, m)
+    F, G, H = (oracle.ntt2d_bins(x, m, wr, wc, bu, bv) for x in (f, g, h))
+    assert [int(p) * int(q) % m for p, q in zip(F, G)] == [int(z) for z in H]
+
+
+def test_conv_integer_full_matches_entries_at_wrap():
+    # the index of g read modulo N, at the split between k <= j and k > j
+    rng = np.random.default_rng(78)
+    N = 64
+    f = rng.integers(0, 1 << 28, N, dtype=np.uint64)
+    g = rng.integers(0, 1 << 28, N, dtype=np.uint64)
+    full = oracle.conv_integer(f, g)
+    for j in (0, 1, N // 2, N - 1):
+        assert int(full[j]) == sum(int(f[k]) * int(g[(j - k) % N]) for k in range(N))
