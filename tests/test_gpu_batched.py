@@ -153,31 +153,37 @@ def test_autotuned_form_matches(nt, lengths):
 
 def test_full_size_batch_in_bench_configuration(nt):
     # the timed workload itself: 4096 x N = 2^16 through the persistent fused
-    # launch.  Every item is checked through its values at the roots of unity
-    # x = 1 and x = -1 (h(x) = f(x) g(x) for x^N = 1, which holds at any size);
-    # sampled entries of a few items against the oracle's direct sum.
+    # launch (the bench's launch configuration).  Every item is checked by the
+    # convolution theorem (Sec. I) at four random bins, H(u) = F(u) G(u) with
+    # the oracle's O(N) transform sums (Eq. 2), and through its values at
+    # x = 1 and x = -1; eight whole items equal the oracle's direct sum (Eq. 1).
     w = si.batch_n65536(4096)
     n, count, N = 16, 4096, 1 << 16
     f, g = si.operands(w)
     desc = nt.BatchDesc([n] * count, si.offsets([n] * count))
-    h = host(nt.conv_batched(dev(f), dev(g), desc, M)).reshape(count, N).astype(np.int64)
-    F = f.reshape(count, N).astype(np.int64)
-    G = g.reshape(count, N).astype(np.int64)
-
-    def at_one(x):
-        return x.sum(axis=1) % M
-
-    def at_minus_one(x):
-        return (x[:, 0::2].sum(axis=1) - x[:, 1::2].sum(axis=1)) % M
-
-    assert np.array_equal(at_one(h), at_one(F) * at_one(G) % M)
-    assert np.array_equal(at_minus_one(h), at_minus_one(F) * at_minus_one(G) % M)
-    assert h.max() < M and h.min() >= 0
+    before = nt.launch_counts()
+    hd = host(nt.conv_batched(dev(f), dev(g), desc, M))
+    assert nt.launch_counts()["fused"] == before["fused"] + 1
+    assert hd.max() < M
+    h = hd.reshape(count, N)
+    F, G = f.reshape(count, N), g.reshape(count, N)
+    root = 256                                          # 2^8, of exact order 2^16
     rng = np.random.default_rng(99)
-    for i in (0, 1, 2047, count - 1, int(rng.integers(0, count))):
-        idx = np.unique(np.r_[0, N - 1, rng.integers(0, N, 8)])
-        ref = oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], M, idx)
-        assert np.array_equal(h[i, idx], ref.astype(np.int64)), i
+    bins = rng.integers(0, N, (count, 4)).astype(np.uint64)
+    bins[:, 0] = rng.integers(1, N // 2, count)        # at least one bin away from 0 and N/2
+    Fb = oracle.ntt_bins_rows(F, M, root, bins)
+    Gb = oracle.ntt_bins_rows(G, M, root, bins)
+    Hb = oracle.ntt_bins_rows(h, M, root, bins)
+    prod = (Fb.astype(object) * Gb.astype(object)) % M
+    bad = np.nonzero(prod.astype(np.uint64) != Hb)
+    assert bad[0].size == 0, ("item", int(bad[0][0]), "bin", int(bins[bad[0][0], bad[1][0]]))
+    Fi, Gi, Hi = F.astype(np.int64), G.astype(np.int64), h.astype(np.int64)
+    at_one = lambda x: x.sum(axis=1) % M
+    at_minus_one = lambda x: (x[:, 0::2].sum(axis=1) - x[:, 1::2].sum(axis=1)) % M
+    assert np.array_equal(at_one(Hi), at_one(Fi) * at_one(Gi) % M)
+    assert np.array_equal(at_minus_one(Hi), at_minus_one(Fi) * at_minus_one(Gi) % M)
+    for i in (0, 1, 2, 1000, 2047, 3000, 4094, count - 1):
+        assert np.array_equal(h[i], oracle.conv_direct(F[i], G[i], M).astype(np.uint32)), i
 
 
 def test_transient_descriptors_many_batches_in_flight(nt):
@@ -227,7 +233,9 @@ def test_first_call_on_fresh_streams_after_release(nt):
     # regression: a stream's work queue is created (zeroed) at its first call;
     # the zeroing must be ordered before that call's persistent kernel on the
     # caller's non-blocking stream, also while another stream keeps the GPU busy
-    lengths = [14, 6, 15, 7, 5, 12, 16, 9]
+    # two items of 2^14 and of 2^16 that are not back to back: the batch keeps
+    # the single multi-length launch (a persistent kernel on the work queue)
+    lengths = [14, 6, 15, 14, 7, 5, 12, 16, 9, 16]
     offs = [int(i) << 16 for i in range(len(lengths))]
     rng = np.random.default_rng(41)
     S = len(lengths) << 16
@@ -244,11 +252,16 @@ def test_first_call_on_fresh_streams_after_release(nt):
         out = torch.zeros_like(f)
         busy_out = torch.zeros_like(busy)
         torch.cuda.synchronize()
+        before = nt.launch_counts()
         with torch.cuda.stream(a):
             nt.conv_batched(busy, busy, busy_desc, M, out=busy_out, stream=a)
         with torch.cuda.stream(b):
             nt.conv_batched(f, g, desc, M, out=out, stream=b)
         torch.cuda.synchronize()
+        after = nt.launch_counts()
+        # the second call created its stream's work queue and ran the
+        # multi-length kernel on it
+        assert after["multi"] == before["multi"] + 1 and after["queue_created"] >= before["queue_created"] + 1
         o = host(out)
         for n, off in zip(lengths, offs):
             assert np.array_equal(o[off:off + (1 << n)], ref[off:off + (1 << n)]), (rep, n)
@@ -258,7 +271,9 @@ def test_release_stream_then_reuse(nt):
     # ntt_release_stream frees a stream's workspaces and work queue; the next
     # call on that stream creates them again and gives the same results (also
     # a stream the library never used may be released)
-    lengths = [16] * 6 + [13, 7, 15]
+    # items of 2^16 and 2^13 not back to back: the multi-length launch, which
+    # needs the stream's work queue
+    lengths = [16, 16, 13, 16, 7, 16, 13, 15, 16, 16]
     offs = si.offsets(lengths)
     rng = np.random.default_rng(43)
     S = int(offs[-1]) + (1 << lengths[-1])
@@ -267,7 +282,7 @@ def test_release_stream_then_reuse(nt):
     desc = nt.BatchDesc(lengths, offs)
     ref = host(nt.conv_batched(f, g, desc, M))
     fh, gh = host(f), host(g)
-    for k, idx in ((7, np.arange(1 << 7)), (6, np.array([0, 1, 4095, 8191]))):
+    for k, idx in ((4, np.arange(1 << 7)), (6, np.array([0, 1, 4095, 8191]))):
         o, n = int(offs[k]), 1 << lengths[k]
         got = ref[o:o + n][idx]
         assert np.array_equal(got, oracle.conv_entries(fh[o:o + n], gh[o:o + n], M, idx).astype(got.dtype)), k
@@ -276,9 +291,12 @@ def test_release_stream_then_reuse(nt):
     for rep in range(3):
         out = torch.zeros_like(f)
         torch.cuda.synchronize()
+        before = nt.launch_counts()
         with torch.cuda.stream(s):
             nt.conv_batched(f, g, desc, M, out=out, stream=s)
         nt.release_stream(s)
+        after = nt.launch_counts()
+        assert after["multi"] == before["multi"] + 1 and after["queue_created"] == before["queue_created"] + 1, rep
         assert np.array_equal(host(out), ref), rep
 
 
@@ -334,23 +352,110 @@ def test_fused_form_at_full_occupancy(nt, n, count):
 
 
 def test_multi_length_launch_with_enough_tasks(nt):
-    # several lengths and more tasks than two thirds of the resident
-    # workgroups: the default form is the single multi-length launch (fewer
-    # tasks take one launch per length); against the per-length form and
-    # sampled oracle entries
+    # several lengths, the items of each long length back to back, and more
+    # tasks than two thirds of the resident workgroups: the default form is the
+    # single multi-length launch because of the task count (with fewer tasks
+    # these lengths would take one launch per length); against the per-length
+    # form and sampled oracle entries
     rng = np.random.default_rng(46)
-    lengths = [int(x) for x in rng.integers(13, 17, 300)] + [int(x) for x in rng.integers(6, 13, 200)]
-    rng.shuffle(lengths)
+    long_ = sorted(int(x) for x in rng.integers(13, 17, 300))
+    short = [int(x) for x in rng.integers(6, 13, 200)]
+    lengths = short[:100] + long_ + short[100:]
     offs = si.offsets(lengths)
     S = int(offs[-1]) + (1 << lengths[-1])
     fh = rng.integers(0, M, S, dtype=np.uint32)
     gh = rng.integers(0, M, S, dtype=np.uint32)
     f, g = dev(fh), dev(gh)
     desc = nt.BatchDesc(lengths, offs)
+    before = nt.launch_counts()
     o = host(nt.conv_batched(f, g, desc, M))
+    assert nt.launch_counts()["multi"] == before["multi"] + 1
     per_class = host(nt.conv_batched(f, g, desc, M, flags=nt.FLAG_PER_CLASS))
     assert np.array_equal(o, per_class)
     for k in (0, 123, 499):
         a, N = int(offs[k]), 1 << lengths[k]
         idx = np.array([0, 1, N - 1])
         assert np.array_equal(o[a:a + N][idx], oracle.conv_entries(fh[a:a + N], gh[a:a + N], M, idx).astype(o.dtype)), k
+
+
+def _few_task_batch(lengths, offs, seed):
+    S = max(int(o) + (1 << n) for n, o in zip(lengths, offs))
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, M, S, dtype=np.uint32), rng.integers(0, M, S, dtype=np.uint32)
+
+
+def _check_items(o, fh, gh, lengths, offs):
+    for n, a in zip(lengths, offs):
+        N, a = 1 << n, int(a)
+        idx = np.arange(N) if n <= 9 else np.array([0, 1, N // 2, N - 1])
+        want = oracle.conv_entries(fh[a:a + N], gh[a:a + N], M, idx).astype(o.dtype)
+        assert np.array_equal(o[a:a + N][idx], want), (n, a)
+
+
+def test_few_tasks_contiguous_long_lengths_take_one_launch_per_length(nt):
+    # fewer tasks than two thirds of the multi-length kernel's resident
+    # workgroups, and every length above 2^12 one back-to-back run: one launch
+    # per length, the long ones in the four-step form that spreads over the chip
+    lengths = [8, 9, 15, 15, 15, 17, 17, 6]
+    offs = si.offsets(lengths)
+    fh, gh = _few_task_batch(lengths, offs, 47)
+    f, g = dev(fh), dev(gh)
+    desc = nt.BatchDesc(lengths, offs)
+    before = nt.launch_counts()
+    o = host(nt.conv_batched(f, g, desc, M))
+    after = nt.launch_counts()
+    assert after["multi"] == before["multi"]
+    assert after["fourstep"] == before["fourstep"] + 2        # 2^15 and 2^17
+    assert after["small"] == before["small"] + 3              # 2^6, 2^8, 2^9
+    assert np.array_equal(o, host(nt.conv_batched(f, g, desc, M, flags=nt.FLAG_PER_CLASS)))
+    _check_items(o, fh, gh, lengths, offs)
+
+
+def test_few_tasks_scattered_long_lengths_keep_the_single_launch(nt):
+    # the same lengths with the items of 2^15 apart: the four-step form needs a
+    # uniform stride, so the batch keeps the single multi-length launch
+    lengths = [15, 8, 15, 9, 15, 17, 17, 6]
+    offs = si.offsets(lengths)
+    fh, gh = _few_task_batch(lengths, offs, 48)
+    f, g = dev(fh), dev(gh)
+    desc = nt.BatchDesc(lengths, offs)
+    before = nt.launch_counts()
+    o = host(nt.conv_batched(f, g, desc, M))
+    after = nt.launch_counts()
+    assert after["multi"] == before["multi"] + 1
+    assert after["fourstep"] == before["fourstep"]
+    assert np.array_equal(o, host(nt.conv_batched(f, g, desc, M, flags=nt.FLAG_PER_CLASS)))
+    _check_items(o, fh, gh, lengths, offs)
+
+
+def test_descriptor_cache_eviction_keeps_descriptors_in_use(nt):
+    # regression: the content-addressed descriptor cache frees its entries when
+    # it is full (256).  Fill it to 255 entries, then run a multi-length batch
+    # whose descriptor is new (the call that fills the cache and evicts); the
+    # result equals the per-length form, and a second round of distinct
+    # descriptors leaves it unchanged
+    nt.release_caches()
+    small = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")
+    before = nt.launch_counts()
+    for i in range(255):
+        # one length, two items apart: a descriptor of its own in the cache
+        nt.conv_batched(small, small, nt.BatchDesc([5, 5], [0, 64 + 32 * i]), M, out=small.clone())
+    mid = nt.launch_counts()
+    assert mid["desc_cached"] - before["desc_cached"] == 255
+    lengths = [16, 9, 16, 13, 5, 13, 12, 16]
+    offs = si.offsets(lengths)
+    fh, gh = _few_task_batch(lengths, offs, 49)
+    f, g = dev(fh), dev(gh)
+    desc = nt.BatchDesc(lengths, offs)
+    o = host(nt.conv_batched(f, g, desc, M))
+    after = nt.launch_counts()
+    assert after["multi"] == mid["multi"] + 1
+    assert after["desc_evicted"] == mid["desc_evicted"]      # 256 entries now: full, nothing freed yet
+    for i in range(40):
+        # offset lists not used above (the cache is keyed by content)
+        nt.conv_batched(small, small, nt.BatchDesc([6, 6], [0, 40000 + 64 * i]), M, out=small.clone())
+    assert nt.launch_counts()["desc_evicted"] > after["desc_evicted"]
+    o2 = host(nt.conv_batched(f, g, desc, M))
+    ref = host(nt.conv_batched(f, g, desc, M, flags=nt.FLAG_PER_CLASS))
+    assert np.array_equal(o, ref) and np.array_equal(o2, ref)
+    _check_items(o, fh, gh, lengths, offs)

@@ -60,3 +60,22 @@ def test_conv2d_in_place_u64_and_euler(nt):
     b = rng.integers(0, me, (64, 16), dtype=np.uint32)
     got = host(nt.conv2d(dev(a), dev(b), me, flags=nt.FLAG_EULER)).reshape(64, 16)
     assert np.array_equal(got, oracle.conv2d_direct(a, b, me).astype(np.uint32))
+
+
+def test_conv2d_benched_size_by_2d_bins(nt):
+    # the timed 2-D workload itself, 4096 x 4096 uniform in [0, m): the 2-D
+    # convolution theorem H(u, v) = F(u, v) G(u, v) at 16 random bins, each
+    # bin the oracle's O(R C) double sum of the 2-D transform (Eq. 2 along each
+    # dimension), which involves every output; plus sampled direct sums
+    R = C = 4096
+    rng = np.random.default_rng(10)
+    f = rng.integers(0, M, (R, C), dtype=np.uint32)
+    g = rng.integers(0, M, (R, C), dtype=np.uint32)
+    h = host(nt.conv2d(dev(f), dev(g), M)).reshape(R, C)
+    w = pow(2, (1 << 19) // 4096, M)                     # exact order 4096
+    bu = np.r_[0, 1, 2048, rng.integers(0, R, 13)].astype(np.uint64)
+    bv = np.r_[0, 4095, 1, rng.integers(0, C, 13)].astype(np.uint64)
+    F, G, H = (oracle.ntt2d_bins(x, M, w, w, bu, bv) for x in (f, g, h))
+    assert [int(a) * int(b) % M for a, b in zip(F, G)] == [int(c) for c in H]
+    idx = np.array([0, R * C - 1, 12345678], np.uint64)
+    assert np.array_equal(h.reshape(-1)[idx.astype(int)], oracle.conv2d_entries(f, g, M, idx).astype(np.uint32))

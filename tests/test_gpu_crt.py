@@ -53,3 +53,36 @@ def test_crt_extreme_values(nt):
     h = host(nt.conv_crt(dev(f), dev(g)))
     assert np.all(h == N * ((1 << 18) - 1) ** 2)
     assert N * ((1 << 18) - 1) ** 2 < M1 * M2
+
+
+def test_crt_benched_size_batch(nt):
+    # the timed CRT workload itself: 4096 x N = 2^16 with 15-bit operands (every
+    # true value below 2^46 < m1 m2, so h is the exact integer convolution).
+    # Every item: the exact integer identity sum_j h(j) = (sum f)(sum g), and
+    # the convolution theorem modulo each prime at two random bins (the
+    # oracle's O(N) transform sums, Eq. 2, with a root of exact order 2^16
+    # modulo m1 and modulo m2); sampled entries against the direct integer sum
+    count, n = 4096, 16
+    N = 1 << n
+    rng = np.random.default_rng(9)
+    f = rng.integers(0, 1 << 15, (count, N), dtype=np.uint32)
+    g = rng.integers(0, 1 << 15, (count, N), dtype=np.uint32)
+    h = host(nt.conv_crt(dev(f), dev(g))).reshape(count, N)
+    sf = f.sum(axis=1, dtype=np.uint64)
+    sg = g.sum(axis=1, dtype=np.uint64)
+    assert np.array_equal(h.sum(axis=1, dtype=np.uint64), sf * sg)       # < 2^62, no wrap
+    assert h.max() < M1 * M2
+    bins = np.random.default_rng(91).integers(1, N, (count, 2)).astype(np.uint64)
+    r1 = pow(2, (1 << 19) // N, M1)
+    z = next(z for z in range(2, 100) if pow(z, (M2 - 1) // 2, M2) == M2 - 1)
+    r2 = pow(z, (M2 - 1) // N, M2)
+    assert pow(r2, N // 2, M2) == M2 - 1 and pow(r1, N // 2, M1) == M1 - 1
+    for m, r in ((M1, r1), (M2, r2)):
+        Fb = oracle.ntt_bins_rows(f, m, r, bins)
+        Gb = oracle.ntt_bins_rows(g, m, r, bins)
+        Hb = oracle.ntt_bins_rows(h % np.uint64(m), m, r, bins)
+        prod = (Fb.astype(object) * Gb.astype(object)) % m
+        assert np.array_equal(prod.astype(np.uint64), Hb), m
+    for i in (0, 2048, count - 1):
+        idx = np.array([0, 1, N - 1], np.uint64)
+        assert np.array_equal(h[i][idx.astype(int)], oracle.conv_integer_entries(f[i], g[i], idx)), i

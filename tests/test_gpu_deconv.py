@@ -122,3 +122,31 @@ def test_deconv_many_rows_through_the_work_queue(nt):
     h = nt.conv_batched(dev(f.reshape(-1)), dev(g0.reshape(-1)), nt.BatchDesc(lens, offs), M)
     g = host(nt.deconvolve(dev(f), h.reshape(rows, N), M))
     assert np.array_equal(g, g0)
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_deconv_refuses_a_capturing_stream(nt):
+    # the quotient's singular flag is read back with a synchronisation, so a
+    # call on a stream under graph capture is refused before anything is
+    # enqueued (torch reports the captured graph as empty); the stream stays
+    # usable and the eager call still recovers g
+    n, N = 10, 1 << 10
+    f, g0 = _draw(1500 + n, N, M), _draw(610, N, M)
+    fd = dev(f)
+    h = nt.conv_circular(fd, dev(g0), M)
+    out = torch.empty_like(fd)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        nt.deconvolve(fd, h, M, out=out, stream=s)       # plans and workspaces in place
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with pytest.raises(nt.NttError) as e:
+        with torch.cuda.graph(graph, stream=s):
+            nt.deconvolve(fd, h, M, out=out, stream=s)
+    assert e.value.name == "NTT_E_UNSUPPORTED"
+    torch.cuda.synchronize()
+    out.zero_()
+    with torch.cuda.stream(s):
+        nt.deconvolve(fd, h, M, out=out, stream=s)
+    s.synchronize()
+    assert np.array_equal(host(out), g0)

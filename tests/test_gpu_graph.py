@@ -32,10 +32,12 @@ def _capture(nt, f, g, desc, h, stream):
     return graph
 
 
-@pytest.mark.parametrize("kind", ["uniform16", "uneven"])
+@pytest.mark.parametrize("kind", ["uniform16", "fused14", "uneven"])
 def test_graph_replay_matches_eager(nt, kind):
     if kind == "uniform16":
-        lengths = (16,) * 40
+        lengths = (16,) * 40            # few items: the multi-launch four-step form
+    elif kind == "fused14":
+        lengths = (14,) * 600           # enough items for the persistent fused kernel
     else:
         lengths = tuple(si.uneven_batch(count=50, seed=7).log2n)
     offs = si.offsets(lengths)
@@ -43,8 +45,12 @@ def test_graph_replay_matches_eager(nt, kind):
     f_h, g_h = si.operands(w)
     f, g = dev(f_h), dev(g_h)
     desc = nt.BatchDesc(lengths, offs)
+    before = nt.launch_counts()
     ref = host(nt.conv_batched(f, g, desc, M))
     torch.cuda.synchronize()
+    form = {"uniform16": "fourstep", "fused14": "fused"}.get(kind)
+    if form:
+        assert nt.launch_counts()[form] == before[form] + 1
 
     stream = torch.cuda.Stream()
     h = torch.zeros_like(f)
@@ -75,13 +81,16 @@ def test_graph_survives_workspace_growth_and_descriptor_churn(nt):
     # push more than the descriptor cache's 256 entries through it; the graph's
     # workspace is retired (not freed) and its descriptors are kept, so the
     # replay still reads live memory and reproduces the eager result
-    lengths = tuple(si.uneven_batch(count=30, seed=9).log2n)
+    lengths = tuple(si.uneven_batch(count=30, seed=9).log2n) + (16, 9, 16)
     offs = si.offsets(lengths)
     w = si.Workload("graph3", M, lengths, 32, M, 23)
     f_h, g_h = si.operands(w)
     f, g = dev(f_h), dev(g_h)
     desc = nt.BatchDesc(lengths, offs)
+    before = nt.launch_counts()
     ref = host(nt.conv_batched(f, g, desc, M))
+    # (the two items of 2^16 apart: the multi-length launch and its descriptor)
+    assert nt.launch_counts()["multi"] == before["multi"] + 1
     stream = torch.cuda.Stream()
     h = torch.zeros_like(f)
     graph = _capture(nt, f, g, desc, h, stream)
@@ -93,13 +102,18 @@ def test_graph_survives_workspace_growth_and_descriptor_churn(nt):
     with torch.cuda.stream(stream):
         nt.conv_batched(big, big, nt.BatchDesc([19] * 64, si.offsets([19] * 64)), M, out=big.clone(),
                         stream=stream)
-    # 300 distinct two-length descriptors through the cache
+    # 300 distinct descriptors through the cache (one length, two items apart:
+    # each needs an offset list), more than its 256 entries, so it evicts
     small = torch.zeros(1 << 15, dtype=torch.int32, device="cuda")
+    before = nt.launch_counts()
     with torch.cuda.stream(stream):
         for i in range(300):
-            nt.conv_batched(small, small, nt.BatchDesc([5, 6], [0, 64 + 64 * i]), M, out=small.clone(),
+            nt.conv_batched(small, small, nt.BatchDesc([5, 5], [0, 64 + 64 * i]), M, out=small.clone(),
                             stream=stream)
     torch.cuda.synchronize()
+    after = nt.launch_counts()
+    assert after["desc_cached"] - before["desc_cached"] == 300
+    assert after["desc_evicted"] > before["desc_evicted"]
     for rep in range(2):
         h.fill_(-1)
         torch.cuda.synchronize()

@@ -127,6 +127,17 @@ def test_n524288_exact_integer_convolution(nt):
     assert np.array_equal(h[idx], oracle.conv_entries(f, g, w.m, idx).astype(np.uint32))
 
 
+@pytest.mark.slow
+def test_n524288_whole_output_against_integer_oracle(nt):
+    """The same N = 2^19 convolution: every output against the oracle's direct
+    integer sum (Eq. 1 without the modulus; exact because 9 N < m), an O(N^2)
+    sum of 2.7e11 products on the host."""
+    w = si.single_n524288_small()
+    f, g = si.operands(w)
+    h = host(nt.conv_circular(dev(f), dev(g), w.m, 2))
+    assert np.array_equal(h.astype(np.uint64), oracle.conv_integer(f, g))
+
+
 def test_inputs_above_m_are_reduced(nt):
     for n in (4, 10, 16):
         N = 1 << n
