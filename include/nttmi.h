@@ -53,7 +53,9 @@ typedef enum {
                                words: m >= 2^46; lengths above 2^22) */
     NTT_E_SINGULAR = 9,     /* conv_deconvolve: a spectral coefficient of the divisor
                                is zero, so no unique quotient exists */
-    NTT_E_TIMEOUT = 10      /* ntt_server_wait: the time limit passed first */
+    NTT_E_TIMEOUT = 10,     /* ntt_server_wait: the time limit passed first */
+    NTT_E_NOPLAN = 11       /* conv_circular_noalloc: the plan of (m, N, root) has not
+                               been built on this device by an earlier call */
 } ntt_status;
 
 /* Flags (bitwise OR). */
@@ -126,6 +128,31 @@ ntt_status ntt_inverse(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_
 ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
                          const void *f, const void *g, void *h, uint32_t flags,
                          void *stream);
+
+/* conv_circular for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * result and arguments as conv_circular.  The call allocates no device or
+ * host memory and never synchronises: lengths above 2^12 keep their 2N
+ * scratch words in a static device array of the library (4 MiB per device,
+ * held until the process ends) instead of a per-stream workspace; shorter
+ * lengths need no scratch.  The first such call on a device looks up the
+ * array's device address, which makes the HIP runtime load the code object
+ * that holds it (a one-time set-up per device, done by the runtime).
+ *   - 2 N (elem_bits / 8) <= 4 MiB: N <= 2^19 with 32-bit words, N <= 2^18
+ *     with 64-bit words; longer: NTT_E_UNSUPPORTED, nothing enqueued.
+ *   - The plan of (m, N, root) (its device tables) must already exist on the
+ *     current device, built by an earlier allocating call with the same m, N
+ *     and root (conv_circular, ntt_forward, ntt_inverse, conv_batched for a
+ *     root of that order); otherwise NTT_E_NOPLAN, nothing enqueued.
+ *   - NTT_FLAG_CHECK_RANGE is refused (NTT_E_UNSUPPORTED): it reads back.
+ * Every call on a device shares that device's one scratch array, which keeps
+ * the last call's contents (each call writes its scratch before reading it):
+ * calls that overlap in time on one device (on different streams, or from
+ * several host threads without ordering) race on it and give undefined
+ * results.  Order them, for example on one stream. */
+ntt_status conv_circular_noalloc(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits,
+                                 const void *f, const void *g, void *h, uint32_t flags,
+                                 void *stream);
 
 /* A batch of independent circular convolutions of uneven power-of-two lengths
  * (see ntt_batch_desc), all modulo the same m.  `root` has exact order

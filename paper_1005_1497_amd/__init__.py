@@ -22,7 +22,7 @@ import numpy as np
 import torch
 
 __all__ = [
-    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "deconvolve", "conv_crt", "conv2d",
+    "NttError", "lib", "ntt_forward", "ntt_inverse", "conv_circular", "conv_circular_noalloc", "conv_batched", "deconvolve", "conv_crt", "conv2d",
     "default_root", "modulus_order", "release_caches", "status_string",
     "FLAG_CHECK_RANGE", "FLAG_PER_ITEM", "FLAG_PER_CLASS", "FLAG_AUTOTUNE", "FLAG_EULER", "FLAG_TRANSIENT", "STATUS",
     "euler_root", "max_log2n", "copy_batch", "launch_counts",
@@ -34,7 +34,7 @@ LIB_PATH = os.path.join(_HERE, "libnttmi.so")
 STATUS = {
     0: "NTT_OK", 1: "NTT_E_ARG", 2: "NTT_E_MODULUS", 3: "NTT_E_LENGTH", 4: "NTT_E_ROOT",
     5: "NTT_E_RANGE", 6: "NTT_E_NOMEM", 7: "NTT_E_DEVICE", 8: "NTT_E_UNSUPPORTED", 9: "NTT_E_SINGULAR",
-    10: "NTT_E_TIMEOUT",
+    10: "NTT_E_TIMEOUT", 11: "NTT_E_NOPLAN",
 }
 FLAG_CHECK_RANGE = 0x1
 FLAG_PER_ITEM = 0x2
@@ -43,7 +43,7 @@ FLAG_AUTOTUNE = 0x8
 FLAG_EULER = 0x10
 FLAG_TRANSIENT = 0x20
 
-EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_batched", "conv_deconvolve", "conv_crt",
+EXPORTS = ("ntt_forward", "ntt_inverse", "conv_circular", "conv_circular_noalloc", "conv_batched", "conv_deconvolve", "conv_crt",
            "conv2d_circular",
            "ntt_default_root",
            "ntt_modulus_order", "ntt_max_log2n", "ntt_euler_root", "ntt_status_string", "ntt_release_caches",
@@ -77,6 +77,8 @@ def _load():
         fn.restype = I32
     L.conv_circular.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, VP]
     L.conv_circular.restype = I32
+    L.conv_circular_noalloc.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, VP]
+    L.conv_circular_noalloc.restype = I32
     L.conv_deconvolve.argtypes = [U64, U32, U64, U32, VP, VP, VP, U32, U32, VP]
     L.conv_deconvolve.restype = I32
     L.conv_crt.argtypes = [U32, VP, VP, VP, U32, U32, VP]
@@ -233,6 +235,24 @@ def conv_circular(f: torch.Tensor, g: torch.Tensor, m: int, root: int | None = N
     _check(lib.conv_circular(int(m), log2n, int(root), bits, ctypes.c_void_p(f.data_ptr()),
                              ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(flags),
                              _stream(stream)), "conv_circular")
+    return out
+
+
+def conv_circular_noalloc(f: torch.Tensor, g: torch.Tensor, m: int, root: int, out: torch.Tensor, flags: int = 0,
+                          stream=None):
+    """conv_circular through the entry point that allocates nothing (static
+    device scratch; the plan of (m, N, root) must exist from an earlier call).
+    The root and the output tensor are required, so this wrapper allocates
+    nothing either."""
+    bits = _words(f, "f")
+    if _words(g, "g") != bits or g.shape != f.shape or f.dim() != 1:
+        raise ValueError("f and g must be 1-D with the same length and word width")
+    if _words(out, "out") != bits or out.shape != f.shape:
+        raise ValueError("out must match f")
+    log2n = _log2(f.numel())
+    _check(lib.conv_circular_noalloc(int(m), log2n, int(root), bits, ctypes.c_void_p(f.data_ptr()),
+                                     ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(flags),
+                                     _stream(stream)), "conv_circular_noalloc")
     return out
 
 

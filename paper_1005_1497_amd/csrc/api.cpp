@@ -146,9 +146,8 @@ int modulus_log2nu(uint64_t m) { return modulus_info(m).first; }
 // Checks m and the word width.  Default: the paper's moduli, primes of which 2
 // is a lambda-root; *lnu = log2 nu bounds the length.  With NTT_FLAG_EULER any
 // prime; *lnu = v2(m - 1) bounds the length.
-ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu, uint32_t flags = 0) {
-    if (elem_bits != 32 && elem_bits != 64) return NTT_E_ARG;
-    const std::pair<int, int> info = modulus_info(m);
+ntt_status check_modulus_info(uint64_t m, uint32_t elem_bits, const std::pair<int, int>& info, int* lnu,
+                              uint32_t flags) {
     *lnu = (flags & NTT_FLAG_EULER) ? info.second : info.first;
     if (*lnu < 0) return NTT_E_MODULUS;
     if (elem_bits == 32 && m >= (1ull << 24)) return NTT_E_MODULUS;
@@ -158,6 +157,11 @@ ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu, uint32_t flag
     // for m < 2^46
     if (elem_bits == 64 && m >= (1ull << 46)) return NTT_E_UNSUPPORTED;
     return NTT_OK;
+}
+
+ntt_status check_modulus(uint64_t m, uint32_t elem_bits, int* lnu, uint32_t flags = 0) {
+    if (elem_bits != 32 && elem_bits != 64) return NTT_E_ARG;
+    return check_modulus_info(m, elem_bits, modulus_info(m), lnu, flags);
 }
 
 // root has exact order 2^k modulo m
@@ -264,6 +268,27 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     auto ins = c.plans.emplace(key, p);
     *out = &ins.first->second;
     return NTT_OK;
+}
+
+// The cached plan of (m, N, root) on the current device, or null; allocates
+// nothing (no insertion into any cache).
+const Plan* find_plan(uint64_t m, uint32_t log2n, uint64_t root) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.plans.find(std::make_tuple(dev, m, (int)log2n, root % m));
+    return it == c.plans.end() ? nullptr : &it->second;
+}
+
+// (log2 nu, v2) of m if cached, without computing or inserting it.
+bool modulus_info_cached(uint64_t m, std::pair<int, int>* out) {
+    Caches& c = caches();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.moduli.find(m);
+    if (it == c.moduli.end()) return false;
+    *out = it->second;
+    return true;
 }
 
 // Per-(device, stream) buffer of at least `bytes`.  Growing it first waits for
@@ -902,6 +927,39 @@ ntt_status conv_circular(uint64_t m, uint32_t log2n, uint64_t root, uint32_t ele
     return conv_one(p, elem_bits, log2n, f, g, h, stream);
 }
 
+ntt_status conv_circular_noalloc(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* f,
+                                 const void* g, void* h, uint32_t flags, void* stream) {
+    // the checks of validate(), from cached modulus data only
+    if (elem_bits != 32 && elem_bits != 64) return NTT_E_ARG;
+    if (flags & NTT_FLAG_CHECK_RANGE) return NTT_E_UNSUPPORTED;   // a read-back needs a workspace
+    std::pair<int, int> info;
+    if (!modulus_info_cached(m, &info)) return NTT_E_NOPLAN;
+    int lnu = 0;
+    ntt_status st = check_modulus_info(m, elem_bits, info, &lnu, flags);
+    if (st != NTT_OK) return st;
+    if ((int)log2n > lnu) return NTT_E_LENGTH;
+    if (!root_has_order(root, log2n, m)) return NTT_E_ROOT;
+    if (log2n > (uint32_t)MAX_LOG2N) return NTT_E_UNSUPPORTED;
+    if (!f || !g || !h) return NTT_E_ARG;
+    const size_t bytes = ((size_t)1 << log2n) * (elem_bits / 8);
+    if (overlap(f, bytes, h, bytes) == 2 || overlap(g, bytes, h, bytes) == 2) return NTT_E_ARG;
+    // the four-step scratch: 2N words of the word width
+    const bool fourstep = (int)log2n > SMALL_MAX_LOG2N;
+    if (fourstep && 2 * bytes > NOALLOC_SCRATCH_BYTES) return NTT_E_UNSUPPORTED;
+    const Plan* p = find_plan(m, log2n, root);
+    if (!p) return NTT_E_NOPLAN;
+    hipStream_t s = (hipStream_t)stream;
+    if (!fourstep) {
+        count(NTT_COUNT_SMALL);
+        return hip_status(launch_conv_small((int)elem_bits, log2n, f, g, h, nullptr, 1, p->dev, s));
+    }
+    void* ws = nullptr;
+    const hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return hip_status(e);
+    count(NTT_COUNT_FOURSTEP);
+    return hip_status(launch_conv_fourstep((int)elem_bits, log2n, f, g, h, 1, 0, ws, p->dev, s));
+}
+
 ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* f,
                            const void* h, void* g, uint32_t batch, uint32_t flags, void* stream) {
     int lnu = 0;
@@ -1279,6 +1337,7 @@ const char* ntt_status_string(ntt_status s) {
         case NTT_E_UNSUPPORTED: return "valid request not supported by the library";
         case NTT_E_SINGULAR: return "a spectral coefficient of the divisor is zero (no unique quotient)";
         case NTT_E_TIMEOUT: return "the time limit passed before the request finished";
+        case NTT_E_NOPLAN: return "no plan for (m, N, root) on this device yet (build it with an earlier call)";
     }
     return "unknown status";
 }

@@ -90,4 +90,11 @@ hipError_t launch_pointwise_mul(int wbits, const void* a, const void* b, void* c
                                 hipStream_t st);
 hipError_t launch_range_check(int wbits, const void* x, uint64_t n, uint64_t m, uint32_t* flag, hipStream_t st);
 
+// Size of the static device scratch (launch_noalloc.hip): the 2N scratch words
+// of one four-step convolution up to 2^19 32-bit or 2^18 64-bit words.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+// Device address of the static scratch on the current device (looked up once
+// per device).
+hipError_t noalloc_scratch(void** out);
+
 }  // namespace nttmi
