@@ -111,6 +111,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def copy_bandwidth(nbytes=1 << 31, reps=10):
+    """Device-to-device copy bandwidth measured in the same run (torch's copy
+    kernel over nbytes, read + write counted): GB/s."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        b.copy_(a)
+    per = _time_ms(lambda: b.copy_(a), reps, st)
+    del a, b
+    return 2 * nbytes / (float(np.median(per)) / 1e3) / 1e9
+
+
+def valu_peaks():
+    """Sustained vector-ALU rates on the device (libnttbench.so), in lane
+    operations per second (an FMA or multiply-add counts one): fp64 FMA, fp64
+    add, int32 add, 24-bit integer multiply-add."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1005_1497_amd", "libnttbench.so")
+    L = ctypes.CDLL(path)
+    L.ntt_bench_valu.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
+                                 ctypes.POINTER(ctypes.c_double)]
+    L.ntt_bench_valu.restype = ctypes.c_int
+    out = {}
+    for kind, name in enumerate(("fp64_fma", "fp64_add", "int32_add", "int32_mad_u24")):
+        ms, ops = ctypes.c_float(0), ctypes.c_double(0)
+        # 256 CUs x 8 workgroups of 256 threads, 256 x 16 x 8 operations per thread
+        rc = L.ntt_bench_valu(kind, 256 * 8, 256, ctypes.byref(ms), ctypes.byref(ops))
+        if rc:
+            raise RuntimeError("ntt_bench_valu(%d) failed: %d" % (kind, rc))
+        out[name] = ops.value / (ms.value / 1e3)
+    return out
+
+
 def cpu_baseline(f, g, m, N, gpu_out=None, budget_s=12.0):
     """The oracle (direct O(N^2) sum of Eq. 1, plain C, all host threads) on a
     bounded sample of items of the same workload.  Returns the baseline and,
@@ -132,6 +168,21 @@ def cpu_baseline(f, g, m, N, gpu_out=None, budget_s=12.0):
         same = all(np.array_equal(gpu_out[i * N:(i + 1) * N], r.astype(gpu_out.dtype)) for i, r in enumerate(refs))
     base = {"value": done / el, "unit": "conv/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the %d items (N=%d), direct O(N^2) sum, %.1f s" % (done, COUNT, N, el)}
+    # the same oracle on one core: a slice of one item's outputs (each the
+    # O(N) direct sum), scaled to whole convolutions
+    oracle.set_threads(1)
+    try:
+        k = N // 32
+        idx = np.arange(k, dtype=np.uint64) * 32
+        t1 = time.perf_counter()
+        part = oracle.conv_entries(f[:N], g[:N], m, idx)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
+    if gpu_out is not None:
+        same = bool(same) and bool(np.array_equal(gpu_out[idx.astype(int)], part.astype(gpu_out.dtype)))
+    base["single_thread"] = {"value": (k / N) / el1, "unit": "conv/s", "cores": 1,
+                             "sample": "%d of the %d outputs of item 0, direct O(N) sums, %.1f s" % (k, N, el1)}
     return base, same
 
 
@@ -145,13 +196,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the per-item comparison form")
     ap.add_argument("--workload", choices=["batch", "serve", "uneven", "single", "deconv", "euler", "crt", "conv2d", "u64",
-                                           "lengths"], default="batch",
+                                           "lengths", "peak", "serve-sweep"], default="batch",
                     help="batch: 4096 x N=2^16 (default); serve: Poisson-arrival serving, 64-bit words; "
                          "uneven: 10000 items, n uniform in [6,19]; single: one N=1024 and one N=2^19 convolution")
     ap.add_argument("--requests", type=int, default=4000, help="serve: timed requests")
     ap.add_argument("--lengths", default="8,10,11,12,13,14,15,16,17,18,19",
                     help="lengths: the log2 N of the uniform 2^26-element batches")
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
+    ap.add_argument("--rhos", default="0.3,0.5,0.7,0.9", help="serve-sweep: the offered loads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (reference kernel for the HBM byte counters)")
     ap.add_argument("--traffic-from", metavar="DIR",
@@ -176,6 +228,8 @@ def main():
         return
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "serve-sweep":
+        return serve_sweep(args)
     if args.workload == "uneven":
         return uneven_bench(args)
     if args.workload == "lengths":
@@ -184,6 +238,14 @@ def main():
         return single_bench(args)
     if args.workload in ("deconv", "euler", "crt", "conv2d", "u64"):
         return variant_bench(args)
+    if args.workload == "peak":
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"metric": "device peaks measured on this GPU", "copy_gbs": copy_bandwidth(),
+                          "valu_lane_ops_per_s": valu_peaks(),
+                          "nominal": {"hbm_gbs": HBM_PEAK_GBS, "valu_lane_ops_per_s": ALU_PEAK_TOPS * 1e12}}),
+              flush=True)
+        return
 
     import torch
     import paper_1005_1497_amd as nt
@@ -258,6 +320,12 @@ def main():
             log("graph replay output differs from the eager output")
         del graph
 
+    # the same GPU's copy bandwidth and vector-ALU rates, measured after the
+    # timed region
+    copy_gbs = copy_bandwidth()
+    peaks = valu_peaks()
+    log("copy %.0f GB/s; fp64 FMA %.1f T lane-ops/s" % (copy_gbs, peaks["fp64_fma"] / 1e12))
+
     value = COUNT * args.steps / wall
     ms = wall / args.steps * 1e3
     alg_bytes = 12 * N * COUNT                     # read f, read g, write h (4-byte words)
@@ -296,6 +364,9 @@ def main():
         "hbm_measured": (None if traffic is None else
                          {"bytes_per_launch": traffic, "gbs": traffic / launch_s / 1e9,
                           "frac_of_8tbs": traffic / launch_s / 1e9 / HBM_PEAK_GBS}),
+        "measured_peaks": {"copy_gbs": copy_gbs, "hbm_frac_of_copy": hbm_gbs / copy_gbs,
+                           "valu_lane_ops_per_s": peaks,
+                           "alu_frac_of_measured_fp64_fma": achieved_tops * 1e12 / peaks["fp64_fma"]},
         "forms": forms,
         "parity_sampled": None,
     }
@@ -695,6 +766,124 @@ def serve_bench(args):
                   "one_launch_per_request_at_same_rate": single_at_rate},
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_sweep(args):
+    """The served workload at several offered loads: --requests timed requests
+    (20000 by default here) after 1000 warm-up ones, lengths 2^n with n uniform
+    in [8, 18], m = 31065037602817 (64-bit words), Poisson arrivals at rho times
+    the saturated throughput of the library's native scheduler; beside each,
+    the same arrivals served one launch sequence per request (Python
+    scheduler, one request per batch) where that form keeps up.  Operand
+    payloads come from a seeded pool of eight per length (the servers copy
+    every request's operands; the values do not change the timing)."""
+    import threading
+
+    import paper_1005_1497_amd.serve as sv
+    import seeded_inputs as si
+
+    m = si.M_U64
+    warm = 1000
+    n = args.requests if args.requests != 4000 else 20000
+    lens = si.served_lengths(warm + n, seed=5)
+    rng = np.random.default_rng(5)
+    pool = {k: [(rng.integers(0, m, 1 << k, dtype=np.uint64), rng.integers(0, m, 1 << k, dtype=np.uint64))
+                for _ in range(8)] for k in range(8, 19)}
+    reqs = [pool[int(k)][i % 8] for i, k in enumerate(lens)]
+    cap = 24
+    rhos = [float(x) for x in args.rhos.split(",")]
+
+    def native(rate, max_batch=512):
+        srv = sv.NativeConvServer(m, capacity_log2=cap, elem_bits=64, streams=4, max_batch=max_batch,
+                                  max_batch_elems=1 << (cap - 2), max_inflight=4)
+        for t in [srv.submit(f, g) for f, g in reqs[:warm]]:
+            srv.result(t)
+        srv.stats(reset=True)
+        body = reqs[warm:]
+        gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
+        tickets = [None] * len(body)
+        ready = threading.Semaphore(0)
+        gc.collect()
+        gc.freeze()
+        t_start = time.perf_counter()
+
+        def producer():
+            nxt = time.perf_counter()
+            for i, ((f, g), gap) in enumerate(zip(body, gaps)):
+                nxt += gap
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(f, g)
+                ready.release()
+
+        sink = np.zeros(1 << 18, dtype=np.uint64)
+
+        def consumer():
+            for i in range(len(body)):
+                ready.acquire()
+                srv.result(tickets[i], out=sink[:tickets[i][1]])
+
+        ths = [threading.Thread(target=producer), threading.Thread(target=consumer)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        el = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        return {"throughput_conv_per_s": len(body) / el, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "mean_batch": st["mean_batch"], "elapsed_s": el}
+
+    def per_request(rate):
+        ex = sv.GpuExecutor(m, capacity_log2=cap, elem_bits=64, streams=4)
+        srv = sv.ConvServer(ex, capacity_log2=cap, max_batch=1, max_inflight=4,
+                            max_batch_elems=1 << (cap - 2)).start()
+        for i in range(warm):
+            srv.submit(*reqs[i])
+        srv.drain()
+        srv.stats = sv.ServeStats()
+        body = range(warm, len(reqs))
+        gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
+        gc.collect()
+        gc.freeze()
+        t_start = time.perf_counter()
+        nxt = time.perf_counter()
+        for i, gap in zip(body, gaps):
+            nxt += gap
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            srv.submit(*reqs[i])
+        srv.drain()
+        el = time.perf_counter() - t_start
+        srv.stop()
+        st = srv.stats
+        return {"throughput_conv_per_s": len(body) / el, "p50_ms": st.percentile(50) * 1e3,
+                "p99_ms": st.percentile(99) * 1e3, "elapsed_s": el}
+
+    sat = native(None)
+    log("native saturated: %.0f conv/s" % sat["throughput_conv_per_s"])
+    single_sat = per_request(None)
+    log("one launch per request, saturated: %.0f conv/s" % single_sat["throughput_conv_per_s"])
+    rows = []
+    for rho in rhos:
+        rate = rho * sat["throughput_conv_per_s"]
+        r = native(rate)
+        row = {"rho": rho, "offered_per_s": rate, "served": r}
+        if rate < 0.95 * single_sat["throughput_conv_per_s"]:
+            row["one_launch_per_request"] = per_request(rate)
+        else:
+            row["one_launch_per_request"] = "offered rate above its saturated throughput (%.0f/s)" % \
+                single_sat["throughput_conv_per_s"]
+        log("rho %.1f: %.0f/s offered, p50 %.3f ms, p99 %.3f ms" % (rho, rate, r["p50_ms"], r["p99_ms"]))
+        rows.append(row)
+    print(json.dumps({"metric": "served exact convolutions: p50/p99 latency across offered loads",
+                      "unit": "ms", "n_gpus": 1, "requests": n, "warmup": warm, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "words": "u64",
+                                 "scheduler": "native (ntt_server_*)", "streams": 4,
+                                 "max_batch_elems": 1 << (cap - 2)},
+                      "saturated": sat, "one_launch_per_request_saturated": single_sat, "sweep": rows}), flush=True)
 
 
 if __name__ == "__main__":

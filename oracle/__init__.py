@@ -48,6 +48,8 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             U64, INT = ctypes.c_uint64, ctypes.c_int
             lib.oracle_threads.restype = INT
+            lib.oracle_set_threads.argtypes = [INT]
+            lib.oracle_set_threads.restype = None
             lib.oracle_is_prime.argtypes = [U64]
             lib.oracle_is_prime.restype = INT
             lib.oracle_powers.argtypes = [U64, U64, U64, _u64p]
@@ -91,6 +93,11 @@ def _p(a: np.ndarray):
 def threads() -> int:
     """Number of OpenMP threads the oracle's parallel loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads of the parallel loops from here on."""
+    _load().oracle_set_threads(int(n))
 
 
 def is_prime(m: int) -> bool:

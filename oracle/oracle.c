@@ -40,6 +40,16 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Number of OpenMP threads for the parallel loops that follow (timing the
+ * oracle on one core and on all of them). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Primality by trial division with every odd d <= sqrt(m).  The method picks
  * m prime so that every nonzero residue has a multiplicative inverse
  * (Sec. III-A). */

@@ -50,6 +50,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+BENCH_SRC = os.path.join(HERE, "bench_csrc", "peak.hip")
+BENCH_LIB = os.path.join(HERE, "libnttbench.so")
+
+
+def build_bench(verbose: bool = False) -> str:
+    """Compile the measurement helpers bench.py uses (vector-ALU peak rates)
+    into libnttbench.so (not part of the convolution library)."""
+    tmp = BENCH_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + HIP_FLAGS + ["-shared", "-x", "hip", BENCH_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, BENCH_LIB)
+    return BENCH_LIB
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_bench(verbose="-v" in sys.argv)
     print(LIB)
