@@ -23,9 +23,7 @@ struct Plan {
     DevPlan dev{};
     double2* dP = nullptr;
     double* dTT = nullptr;
-    double* dTTi = nullptr;
     uint32_t* dTT32 = nullptr;
-    uint32_t* dTTi32 = nullptr;
 };
 
 struct Buf {
@@ -223,31 +221,20 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     if (he == hipSuccess && (int)log2n > SMALL_MAX_LOG2N) {
         const int la = fs_la((int)log2n), lb = (int)log2n - la;
         const uint64_t A = 1ull << la, B = 1ull << lb;
-        std::vector<double> tt(N), tti(N);
+        std::vector<double> tt(N);
         for (uint64_t u2 = 0; u2 < B; ++u2)
-            for (uint64_t t1 = 0; t1 < A; ++t1) {
-                const uint64_t e = (t1 * u2) & (N - 1);
-                tt[u2 * A + t1] = hP[e].x;
-                tti[u2 * A + t1] = hP[(N - e) & (N - 1)].x;
-            }
+            for (uint64_t t1 = 0; t1 < A; ++t1) tt[u2 * A + t1] = hP[(t1 * u2) & (N - 1)].x;
         he = upload(&p.dTT, tt);
-        if (he == hipSuccess) he = upload(&p.dTTi, tti);
         if (he == hipSuccess && m < (1ull << 32)) {
-            std::vector<uint32_t> t32(N), ti32(N);
-            for (uint64_t e = 0; e < N; ++e) {
-                t32[e] = (uint32_t)tt[e];
-                ti32[e] = (uint32_t)tti[e];
-            }
+            std::vector<uint32_t> t32(N);
+            for (uint64_t e = 0; e < N; ++e) t32[e] = (uint32_t)tt[e];
             he = upload(&p.dTT32, t32);
-            if (he == hipSuccess) he = upload(&p.dTTi32, ti32);
         }
     }
     if (he != hipSuccess) {
         if (p.dP) (void)hipFree(p.dP);
         if (p.dTT) (void)hipFree(p.dTT);
-        if (p.dTTi) (void)hipFree(p.dTTi);
         if (p.dTT32) (void)hipFree(p.dTT32);
-        if (p.dTTi32) (void)hipFree(p.dTTi32);
         return hip_status(he);
     }
     // N^-1 mod m, the multiplicative inverse of N (Appendix A): 2^(nu - n)
@@ -257,9 +244,7 @@ ntt_status get_plan(uint64_t m, uint32_t log2n, uint64_t root, int lnu, const Pl
     (void)lnu;
     p.dev.P = p.dP;
     p.dev.TT = p.dTT;
-    p.dev.TTi = p.dTTi;
     p.dev.TT32 = p.dTT32;
-    p.dev.TTi32 = p.dTTi32;
     p.dev.M = make_modc(m);
     p.dev.ninv = (double)ninv;
     p.dev.ninvq = (double)ninv / (double)m;
@@ -1356,9 +1341,7 @@ void ntt_release_caches(void) {
     for (auto& kv : c.plans) {
         if (kv.second.dP) (void)hipFree(kv.second.dP);
         if (kv.second.dTT) (void)hipFree(kv.second.dTT);
-        if (kv.second.dTTi) (void)hipFree(kv.second.dTTi);
         if (kv.second.dTT32) (void)hipFree(kv.second.dTT32);
-        if (kv.second.dTTi32) (void)hipFree(kv.second.dTTi32);
     }
     c.plans.clear();
     for (auto& kv : c.work) if (kv.second.ptr) (void)hipFree(kv.second.ptr);

@@ -179,11 +179,15 @@ __device__ __forceinline__ int tw_index(int eL, int lshift, int nmask) {
 // at position Blk::pos0(j, i) of sequence s (reduced); on exit v[i] holds the
 // output at Blk::posL(j, i).  `ldsbuf` must be free on entry and is free on
 // exit.  P is the power table of the item's N-th root (N = L << lshift).
-template <class W, int L, int S, int ORD, bool INV, class TWF>
+// REVS (SEQ_FAST only): the last exchange hands sequence S - 1 - s to work
+// item s, so on exit v holds the transform of sequence S - 1 - s (the
+// twiddles depend on positions only).
+template <class W, int L, int S, int ORD, bool INV, bool REVS = false, class TWF>
 __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, int j,
                                              const double2* __restrict__ P, int lshift, int nmask,
                                              const ModC& M, TWF twf) {
     using B = Blk<L, S, ORD>;
+    static_assert(!REVS || (ORD == SEQ_FAST && B::NP > 1), "sequence reversal: SEQ_FAST blocks with an exchange");
     constexpr int E = B::E;
     // keep the uniform twiddle loads inside this transform (not hoisted into
     // the caller's loops, where several transforms' tables would pile up)
@@ -213,8 +217,9 @@ __device__ __forceinline__ void block_dft_tw(double* v, double* ldsbuf, int s, i
         (void)Vp;
         xch_sync<B::WAVE_LOCAL>();
         // read inputs of this pass (radix 16, one virtual item jv = j)
+        const int sr = (REVS && p == B::NP - 1) ? S - 1 - s : s;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = ldsbuf[B::lds(s, j + r * (L / 16))];
+        for (int r = 0; r < 16; ++r) v[r] = ldsbuf[B::lds(sr, j + r * (L / 16))];
         xch_sync<B::WAVE_LOCAL>();
         // inter-pass twiddles w_{16 Ns}^(r k) = w_L^((L/(16 Ns)) r k), k = j mod Ns
         twf(v, p, Ns, j & (Ns - 1));

@@ -275,14 +275,15 @@ struct Buf {
     }
 };
 
-// Four-step twiddle w^(+-t1 u2) from the plan's tables: 32-bit words when the
-// modulus fits (half the bytes and registers of the fp64 table).
+// Four-step twiddle w^(t1 u2) from the plan's table (the inverse transforms
+// use it too): 32-bit words when the modulus fits (half the bytes and
+// registers of the fp64 table).
 template <class W>
 struct Tw4 {
     using T = typename std::conditional<W::WB == 4, uint32_t, double>::type;
-    __device__ static __forceinline__ Buf buf(const DevPlan& p, bool inv, uint32_t n) {
-        if constexpr (W::WB == 4) return Buf(inv ? p.TTi32 : p.TT32, n * 4u);
-        else return Buf(inv ? p.TTi : p.TT, n * 8u);
+    __device__ static __forceinline__ Buf buf(const DevPlan& p, uint32_t n) {
+        if constexpr (W::WB == 4) return Buf(p.TT32, n * 4u);
+        else return Buf(p.TT, n * 8u);
     }
     __device__ static __forceinline__ T ld(const Buf& b, uint32_t ve, uint32_t se) {
         if constexpr (W::WB == 4) return b.ld32(ve * 4u, se * 4u);
@@ -331,10 +332,12 @@ __device__ __forceinline__ void st_scr(const Buf& b, double y, uint32_t ve, uint
 
 // Shared-memory layout of a four-step workgroup: the pass exchange buffer and
 // the per-pass twiddle tables of the column (length B) and row (length A)
-// transforms, forward and inverse.  Table entries are (w, w/m) pairs, which
-// save the quotient multiply of every inter-pass twiddle, unless the pairs
-// would push the workgroup out of two-per-CU residency or out of LDS; then
-// they hold w alone and w/m is formed at use.
+// transforms.  Only forward tables: every inverse transform runs as the
+// forward transform with its output index negated (x(t) = N^-1 F(X)(-t) for
+// the forward transform F of Eq. 2, which is Eq. 3).  Table entries are
+// (w, w/m) pairs, which save the quotient multiply of every inter-pass
+// twiddle, unless the pairs would push the workgroup out of two-per-CU
+// residency or out of LDS; then they hold w alone and w/m is formed at use.
 constexpr int LDS_HALF_CU = 80 * 1024;
 template <int LOGN>
 struct FSLds {
@@ -343,7 +346,7 @@ struct FSLds {
     static constexpr int TC = PassTab<G::Bn>::SIZE;   // entries per column table
     static constexpr int TR = PassTab<G::A>::SIZE;    // entries per row table
     static constexpr int XCH2 = (G::XCH + 1) & ~1;     // tables start 16-byte aligned
-    static constexpr int ENTRIES = 2 * TC + (SAME ? 0 : 2 * TR);
+    static constexpr int ENTRIES = TC + (SAME ? 0 : TR);
     static constexpr int BYTES1 = 8 * (XCH2 + ENTRIES);
     static constexpr int BYTES2 = 8 * (XCH2 + 2 * ENTRIES);
     static constexpr bool PAIRS = BYTES2 <= LDS_HALF_CU || (BYTES1 > LDS_HALF_CU && BYTES2 <= 150 * 1024);
@@ -351,12 +354,10 @@ struct FSLds {
     static constexpr int WORDS = PAIRS ? BYTES2 / 8 : BYTES1 / 8;
     double* xch;
     const Entry* colf;
-    const Entry* coli;
     const Entry* rowf;
-    const Entry* rowi;
 };
 
-template <int L, bool INV, class T>
+template <int L, class T>
 __device__ __forceinline__ void fill_pass_tab(T* t, const DevPlan& p, int logn) {
     using PT = PassTab<L>;
     using B = Blk<L, 1, SEQ_FAST>;
@@ -367,7 +368,7 @@ __device__ __forceinline__ void fill_pass_tab(T* t, const DevPlan& p, int logn) 
         const int cnt = 16 * PT::ns(q);
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const int k = e >> 4, r = e & 15;
-            const double2 w = p.P[tw_index<INV>(PT::expo(q, k, r), lshift, nmask)];
+            const double2 w = p.P[tw_index<false>(PT::expo(q, k, r), lshift, nmask)];
             if constexpr (std::is_same<T, double2>::value) t[PT::off(q) + k * PT::ROW + r] = w;
             else t[PT::off(q) + k * PT::ROW + r] = w.x;
         }
@@ -382,9 +383,7 @@ __device__ __forceinline__ FSLds<LOGN> fs_lds_layout(double* lds) {
     L.xch = lds;
     typename FL::Entry* t = reinterpret_cast<typename FL::Entry*>(lds + FL::XCH2);
     L.colf = t;
-    L.coli = t + FL::TC;
-    L.rowf = FL::SAME ? L.colf : t + 2 * FL::TC;
-    L.rowi = FL::SAME ? L.coli : t + 2 * FL::TC + FL::TR;
+    L.rowf = FL::SAME ? L.colf : t + FL::TC;
     return L;
 }
 
@@ -394,12 +393,8 @@ __device__ __forceinline__ void fs_lds_fill(const FSLds<LOGN>& L, const DevPlan&
     using G = FS<LOGN>;
     using FL = FSLds<LOGN>;
     using E = typename FL::Entry;
-    fill_pass_tab<G::Bn, false>(const_cast<E*>(L.colf), p, LOGN);
-    fill_pass_tab<G::Bn, true>(const_cast<E*>(L.coli), p, LOGN);
-    if (!FL::SAME) {
-        fill_pass_tab<G::A, false>(const_cast<E*>(L.rowf), p, LOGN);
-        fill_pass_tab<G::A, true>(const_cast<E*>(L.rowi), p, LOGN);
-    }
+    fill_pass_tab<G::Bn>(const_cast<E*>(L.colf), p, LOGN);
+    if (!FL::SAME) fill_pass_tab<G::A>(const_cast<E*>(L.rowf), p, LOGN);
     __syncthreads();
 }
 
@@ -465,7 +460,7 @@ __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typena
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int t1 = c0 + s;
-    const Buf by(Y, G::N * W::SB), bt = Tw4<W>::buf(p, false, G::N);
+    const Buf by(Y, G::N * W::SB), bt = Tw4<W>::buf(p, G::N);
     double v[B::E];
     // four-step twiddles, loaded ahead of the transform
     typename Tw4<W>::T tw4[B::E];
@@ -487,7 +482,9 @@ __device__ __forceinline__ void col_fwd_block(const typename W::word* x, typenam
 }
 
 // Row phase of a convolution: for rows r0..r0+SR, forward(f row), forward(g
-// row), product with N^-1, inverse, times w^-(t1 u2), back into Yf.
+// row), product with N^-1, then the first half of the inverse four-step as a
+// forward one (row transforms, times w^(t1 u2)), back into Yf; the inverse
+// column phase negates the output index.
 template <class W, int LOGN>
 struct RowIn {
     typename W::sword f[FS<LOGN>::BR::E];
@@ -525,7 +522,7 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf bf(Yf, G::N * W::SB), bt = Tw4<W>::buf(p, true, G::N);
+    const Buf bf(Yf, G::N * W::SB), bt = Tw4<W>::buf(p, G::N);
     const uint32_t rowoff = (uint32_t)(u2 * G::A + j);
     double F[B::E], v[B::E];
     if constexpr (LOCKSTEP) {
@@ -564,8 +561,10 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     typename Tw4<W>::T tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, rowoff, B::posL(0, i));
-    block_dft_tw<W, G::A, G::SR, POS_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                 twtab<W, G::A>(L.rowi, M));
+    // the inverse rows: forward transforms (the output index is negated by the
+    // inverse column phase), then the twiddle w^(u2 s1) of the forward four-step
+    block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                  twtab<W, G::A>(L.rowf, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i));
 }
@@ -577,12 +576,22 @@ __device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const type
     row_conv_compute<W, LOGN, OP, LOCKSTEP>(row_conv_load<W, LOGN>(Yf, Yg, r0), Yf, r0, p, L, singular);
 }
 
-// Column phase, inverse: length-B inverse transforms of scratch columns,
-// optional N^-1, canonical store to x[t1 + A t2].
+// Column phase, inverse: length-B transforms of scratch columns, optional
+// N^-1, canonical store.  Each transform is the forward one and its output
+// index is negated (Eq. 3 as the forward transform of Eq. 2 read at -t), so
+// the block that stores destination columns c0 .. c0 + SC - 1 transforms the
+// source columns t1 = -(c0 + s) mod A: the SC columns ending at A - c0, taken
+// in ascending order, one of them (the last, A - c0 = A) wrapping to column 0.
 template <class W, int LOGN>
 struct ColInvIn {
     typename W::sword w[FS<LOGN>::BC::E];
 };
+
+template <int LOGN>
+__device__ __forceinline__ uint32_t col_inv_src(int c0, int s) {
+    using G = FS<LOGN>;
+    return (uint32_t)(G::A - c0 - (G::SC - 1) + s) & (uint32_t)(G::A - 1);
+}
 
 template <class W, int LOGN>
 __device__ __forceinline__ ColInvIn<W, LOGN> col_inv_load(const typename W::sword* Y, int c0) {
@@ -591,11 +600,40 @@ __device__ __forceinline__ ColInvIn<W, LOGN> col_inv_load(const typename W::swor
     int s, j;
     B::item(threadIdx.x, s, j);
     const Buf by(Y, G::N * W::SB);
+    const uint32_t off = (uint32_t)(j * G::A) + col_inv_src<LOGN>(c0, s);
     ColInvIn<W, LOGN> in;
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) in.w[i] = ld_scr_raw<W>(by, j * G::A + c0 + s, B::pos0(0, i) * G::A);
+    for (int i = 0; i < B::E; ++i) in.w[i] = ld_scr_raw<W>(by, off, B::pos0(0, i) * G::A);
     return in;
 }
+
+// Where the inverse column phase stores.  The transform of the block's last
+// exchange reverses the sequences (block_dft_tw's REVS), so work item s ends
+// with the transform of source column t1 = -(c0 + s) mod A, whose elements
+// t = t1 + A t2 (t2 = j + posL(0, i)) belong at -t mod N: destination column
+// c0 + s, ascending with s, so that every store of a block fills whole cache
+// lines.  For t1 != 0 the destination row is B - 1 - t2; since posL(0, i) =
+// i B / 16, that is (W - 1 - j) + posL(0, 15 - i): register i goes where
+// register 15 - i of lane (c0 + s, W - 1 - j) would, so one per-lane offset and
+// the reversed register order give every address.  Column 0 (c0 = s = 0) maps
+// to rows B - t2 mod B, one row further; its element t = 0 stays at 0 (stored
+// by the item with j = 0 on its own).
+template <int LOGN>
+struct NegStore {
+    uint32_t lane;   // per-lane element offset
+    bool zero;       // the lane holding t = 0 (its register 0)
+    __device__ __forceinline__ NegStore(int c0, int s, int j) {
+        using G = FS<LOGN>;
+        using B = typename G::BC;
+        static_assert(B::E == 16 && B::NP > 1, "negated store: radix-16 column passes");
+        const uint32_t d = (uint32_t)(c0 + s);   // destination column
+        const uint32_t jr = (uint32_t)(B::W - 1 - j) + (d == 0 ? 1u : 0u);
+        lane = d + G::A * jr;
+        zero = d == 0 && j == 0;
+    }
+    // uniform element offset of register i
+    __device__ static constexpr uint32_t reg(int i) { return FS<LOGN>::A * FS<LOGN>::BC::posL(0, 15 - i); }
+};
 
 template <class W, int LOGN, bool SCALE, bool CRT = false>
 __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typename W::word* x, int c0,
@@ -606,32 +644,39 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
     int s, j;
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
-    const uint32_t off = (uint32_t)(j * G::A + c0 + s);
+    const NegStore<LOGN> ns(c0, s, j);
     double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::from_s(in.w[i]);
-    // the first residues, loaded ahead of the transform that hides their latency
+    // the first residues (at the output positions), loaded ahead of the
+    // transform that hides their latency; lane t = 0's register 0 (beyond the
+    // buffer at the negated offset, so read as 0) reloaded from position 0
     uint32_t a1v[CRT ? B::E : 1];
     if constexpr (CRT) {
         const Buf ba(crt.a1, G::N * 4u);
 #pragma unroll
-        for (int i = 0; i < B::E; ++i) a1v[i] = ba.ld32s(off * 4u, B::posL(0, i) * G::A * 4u);
+        for (int i = 0; i < B::E; ++i) a1v[i] = ba.ld32s(ns.lane * 4u, NegStore<LOGN>::reg(i) * 4u);
+        if (ns.zero) a1v[0] = ba.ld32s(0u, 0u);
     }
-    block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
-                                                  twtab<W, G::Bn>(L.coli, M));
+    block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, false, true>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
+                                                            twtab<W, G::Bn>(L.colf, M));
     if constexpr (!CRT) {
         const Buf bx(x, G::N * W::WB);
+        typename W::word out[B::E];
 #pragma unroll
         for (int i = 0; i < B::E; ++i) {
             const double y = SCALE ? W::mul_tw(v[i], make_double2(p.ninv, p.ninvq), M) : v[i];
-            st_word_s<W>(bx, W::canon(y, M), off, B::posL(0, i) * G::A);
+            out[i] = W::canon(y, M);
+            st_word_s<W>(bx, out[i], ns.lane, NegStore<LOGN>::reg(i));   // lane t = 0: dropped (beyond the buffer)
         }
+        if (ns.zero) st_word_s<W>(bx, out[0], 0u, 0u);
     } else {
         // y is this element mod m2 (= M.m) and a1 its residue mod m1: the
         // integer in [0, m1 m2) with both residues is a1 + m1 t,
         // t = ((y - a1) m1^-1) mod m2 (every product below 2^47)
         const Buf bh(crt.h, G::N * 8u);
         const double c = (double)crt.c;
+        uint64_t out[B::E];
 #pragma unroll
         for (int i = 0; i < B::E; ++i) {
             const uint32_t a1 = a1v[i];
@@ -640,8 +685,10 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
             double t = mulmod_var(d, c, M);
             t = (t < 0.0) ? t + M.m : t;
             t = (t >= M.m) ? t - M.m : t;
-            bh.st64((uint64_t)a1 + (uint64_t)crt.m1 * (uint64_t)t, off * 8u, B::posL(0, i) * G::A * 8u);
+            out[i] = (uint64_t)a1 + (uint64_t)crt.m1 * (uint64_t)t;
+            bh.st64(out[i], ns.lane * 8u, NegStore<LOGN>::reg(i) * 8u);
         }
+        if (ns.zero) bh.st64(out[0], 0u, 0u);
     }
 }
 
@@ -672,7 +719,8 @@ __device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, ty
 }
 
 // Row phase of the natural-order inverse transform: from X[u2 + B u1] to
-// scratch rows, times w^-(t1 u2).
+// scratch rows: forward row transforms times w^(u2 s1) (the inverse column
+// phase negates the output index).
 template <class W, int LOGN>
 __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typename W::sword* Y, int r0,
                                                   const DevPlan& p, const FSLds<LOGN>& L) {
@@ -682,15 +730,15 @@ __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typ
     B::item(threadIdx.x, s, j);
     const ModC M = p.M;
     const int u2 = r0 + s;
-    const Buf bx(X, G::N * W::WB), by(Y, G::N * W::SB), bt = Tw4<W>::buf(p, true, G::N);
+    const Buf bx(X, G::N * W::WB), by(Y, G::N * W::SB), bt = Tw4<W>::buf(p, G::N);
     double v[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(ld_word<W>(bx, u2 + G::Bn * j, G::Bn * B::pos0(0, i)), M);
     typename Tw4<W>::T tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, u2 * G::A + j, B::posL(0, i));
-    block_dft_tw<W, G::A, G::SR, SEQ_FAST, true>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
-                                                 twtab<W, G::A>(L.rowi, M));
+    block_dft_tw<W, G::A, G::SR, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
+                                                  twtab<W, G::A>(L.rowf, M));
 #pragma unroll
     for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), u2 * G::A + j, B::posL(0, i));
 }
@@ -760,6 +808,9 @@ struct FusedCfg {
     // minimum waves per SIMD (the second __launch_bounds__ argument): four
     // for two 512-thread workgroups per CU, i.e. at most 128 VGPRs
     static constexpr int WAVES_PER_EU = TWO ? 4 : 2;
+    // phases with software prefetch (fused_conv_item): all of them at one
+    // workgroup per CU
+    static constexpr int PF = TWO ? 0 : 15;
 };
 
 // Work queue of a persistent launch: q[0] is the next item, q[1] counts the
@@ -785,9 +836,12 @@ __device__ __forceinline__ void queue_leave(uint32_t* q) {
 // One convolution of length 2^LOGN by the four-step path, start to finish, in
 // one workgroup: columns of f and of g into the scratch Yf, Yg (N words each),
 // rows (forward f, forward g, product with N^-1, inverse) back into Yf, then
-// the inverse columns into h.  With PREFETCH each block's loads are issued
-// before the previous block is transformed.  Ends with a barrier.
-template <class W, int LOGN, bool PREFETCH, int OP = OP_MUL>
+// the inverse columns into h.  PF selects the phases whose blocks issue their
+// loads before the previous block is transformed (software prefetch into
+// registers): bit 0 the forward columns, bit 1 the rows, bit 2 the inverse
+// columns; bit 3 transforms the f and g rows pass by pass together
+// (row_conv_compute's LOCKSTEP).  Ends with a barrier.
+template <class W, int LOGN, int PF, int OP = OP_MUL>
 __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, const typename W::word* gi,
                                                 typename W::word* hi, typename W::sword* Yf,
                                                 typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN>& L,
@@ -796,15 +850,9 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
     constexpr int CL = G::A - G::SC;
     constexpr int SOP = OP == OP_DIV ? OP_DIV : OP_MUL;   // the pointwise step
     constexpr bool CRT = OP == OP_CRT;                    // the final store
-    if constexpr (!PREFETCH) {
+    if constexpr (!(PF & 1)) {
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(fi, Yf, c0, p, L);
         for (int c0 = 0; c0 < G::A; c0 += G::SC) col_fwd_block<W, LOGN>(gi, Yg, c0, p, L);
-        __syncthreads();
-        for (int r0 = 0; r0 < G::Bn; r0 += G::SR) row_conv_block<W, LOGN, SOP, false>(Yf, Yg, r0, p, L, singular);
-        __syncthreads();
-        for (int c0 = 0; c0 < G::A; c0 += G::SC)
-            col_inv_compute<W, LOGN, false, CRT>(col_inv_load<W, LOGN>(Yf, c0), hi, c0, p, L, crt);
-        __syncthreads();
     } else {
         ColIn<W, LOGN> cin = col_fwd_load<W, LOGN>(fi, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
@@ -823,15 +871,25 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
             cin = nxt;
         }
         col_fwd_compute<W, LOGN>(cin, Yg, CL, p, L);
-        __syncthreads();
+    }
+    __syncthreads();
+    if constexpr (!(PF & 2)) {
+        for (int r0 = 0; r0 < G::Bn; r0 += G::SR)
+            row_conv_block<W, LOGN, SOP, (PF & 8) != 0>(Yf, Yg, r0, p, L, singular);
+    } else {
         RowIn<W, LOGN> rin = row_conv_load<W, LOGN>(Yf, Yg, 0);
         for (int r0 = 0; r0 < G::Bn - G::SR; r0 += G::SR) {
             const RowIn<W, LOGN> nxt = row_conv_load<W, LOGN>(Yf, Yg, r0 + G::SR);
-            row_conv_compute<W, LOGN, SOP>(rin, Yf, r0, p, L, singular);
+            row_conv_compute<W, LOGN, SOP, (PF & 8) != 0>(rin, Yf, r0, p, L, singular);
             rin = nxt;
         }
-        row_conv_compute<W, LOGN, SOP>(rin, Yf, G::Bn - G::SR, p, L, singular);
-        __syncthreads();
+        row_conv_compute<W, LOGN, SOP, (PF & 8) != 0>(rin, Yf, G::Bn - G::SR, p, L, singular);
+    }
+    __syncthreads();
+    if constexpr (!(PF & 4)) {
+        for (int c0 = 0; c0 < G::A; c0 += G::SC)
+            col_inv_compute<W, LOGN, false, CRT>(col_inv_load<W, LOGN>(Yf, c0), hi, c0, p, L, crt);
+    } else {
         ColInvIn<W, LOGN> iin = col_inv_load<W, LOGN>(Yf, 0);
         for (int c0 = 0; c0 < CL; c0 += G::SC) {
             const ColInvIn<W, LOGN> nxt = col_inv_load<W, LOGN>(Yf, c0 + G::SC);
@@ -839,8 +897,8 @@ __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, cons
             iin = nxt;
         }
         col_inv_compute<W, LOGN, false, CRT>(iin, hi, CL, p, L, crt);
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 // Persistent fused convolution of a uniform-length batch: one workgroup owns
@@ -866,8 +924,8 @@ __global__ __launch_bounds__(512, (FusedCfg<W, LOGN, OP>::WAVES_PER_EU)) void k_
             ci.a1 += off;
             ci.h += off;
         }
-        fused_conv_item<W, LOGN, !FusedCfg<W, LOGN, OP>::TWO, OP>(f + off, g + off, h + off, Yf, Yg, p, L,
-                                                                 singular, ci);
+        fused_conv_item<W, LOGN, FusedCfg<W, LOGN, OP>::PF, OP>(f + off, g + off, h + off, Yf, Yg, p, L, singular,
+                                                                ci);
     }
     queue_leave(queue);
 }
@@ -917,7 +975,7 @@ __device__ __forceinline__ uint32_t multi_run(uint32_t t, const typename W::word
         fs_lds_fill<K>(L, p);
         do {
             const uint64_t o = toffs[tasks[t].first];
-            fused_conv_item<W, K, true>(f + o, g + o, h + o, Y, Y + (1 << K), p, L);
+            fused_conv_item<W, K, 15>(f + o, g + o, h + o, Y, Y + (1 << K), p, L);
             t = __builtin_amdgcn_readfirstlane(queue_take(queue, ticket));
         } while (t < ntasks && tasks[t].logn == (uint32_t)K);
     } else {

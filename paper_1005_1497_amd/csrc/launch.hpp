@@ -10,10 +10,9 @@ namespace nttmi {
 // every kernel by value.
 struct DevPlan {
     const double2* P;    // P[e] = (w^e, w^e / m), e < N: powers of the N-th root
-    const double* TT;    // four-step twiddles TT[u2 * A + t1] = w^(t1 u2) (large N only)
-    const double* TTi;   // w^-(t1 u2)
+    const double* TT;    // four-step twiddles TT[u2 * A + t1] = w^(t1 u2) (large N only; the
+                         // inverse transforms use them too: they run as forward transforms)
     const uint32_t* TT32;   // the same as 32-bit words (m < 2^32 only)
-    const uint32_t* TTi32;
     ModC M;
     double ninv, ninvq;  // N^-1 mod m and N^-1 / m
     int logn, nmask;
