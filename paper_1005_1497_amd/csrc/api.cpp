@@ -305,8 +305,10 @@ ntt_status get_buf(std::map<std::pair<int, void*>, Buf>& pool, void* stream, siz
 // zeroed once here, on the stream itself so that the first kernel is ordered
 // after the zeroing (a plain hipMemset runs on the null stream, which does not
 // order the non-blocking streams callers use); every launch leaves them zero
-// again.  Creation is refused while the stream is being captured (a call on
-// the stream before the capture creates the queue).
+// again.  Creation is refused while the stream is being captured.  Only the
+// persistent forms (k_conv_fused, k_conv_multi) create it, so a call made
+// before a capture prepares the queue only if it takes one of those forms:
+// the same batch shape on the same stream does.
 ntt_status get_queue(void* stream, uint32_t** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NTT_E_DEVICE;
