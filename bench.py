@@ -774,9 +774,11 @@ def serve_sweep(args):
     in [8, 18], m = 31065037602817 (64-bit words), Poisson arrivals at rho times
     the saturated throughput of the library's native scheduler; beside each,
     the same arrivals served one launch sequence per request (Python
-    scheduler, one request per batch) where that form keeps up.  Operand
-    payloads come from a seeded pool of eight per length (the servers copy
-    every request's operands; the values do not change the timing)."""
+    scheduler, one request per batch) where that form keeps up, and that form
+    at rho times its own saturated throughput.  Every request has operands of
+    its own: slices at seeded random offsets of one 2^23-word random buffer per
+    operand (distinct contents without 16 GB of host payloads; the servers
+    copy every request's operands)."""
     import threading
 
     import paper_1005_1497_amd.serve as sv
@@ -787,9 +789,14 @@ def serve_sweep(args):
     n = args.requests if args.requests != 4000 else 20000
     lens = si.served_lengths(warm + n, seed=5)
     rng = np.random.default_rng(5)
-    pool = {k: [(rng.integers(0, m, 1 << k, dtype=np.uint64), rng.integers(0, m, 1 << k, dtype=np.uint64))
-                for _ in range(8)] for k in range(8, 19)}
-    reqs = [pool[int(k)][i % 8] for i, k in enumerate(lens)]
+    big = 1 << 23
+    fbuf = rng.integers(0, m, big, dtype=np.uint64)
+    gbuf = rng.integers(0, m, big, dtype=np.uint64)
+    reqs = []
+    for k in lens:
+        nk = 1 << int(k)
+        a, b = rng.integers(0, big - nk + 1, 2)
+        reqs.append((fbuf[a:a + nk], gbuf[b:b + nk]))
     cap = 24
     rhos = [float(x) for x in args.rhos.split(",")]
 
@@ -876,6 +883,8 @@ def serve_sweep(args):
         else:
             row["one_launch_per_request"] = "offered rate above its saturated throughput (%.0f/s)" % \
                 single_sat["throughput_conv_per_s"]
+        own = rho * single_sat["throughput_conv_per_s"]
+        row["one_launch_per_request_at_own_rho"] = {"offered_per_s": own, "served": per_request(own)}
         log("rho %.1f: %.0f/s offered, p50 %.3f ms, p99 %.3f ms" % (rho, rate, r["p50_ms"], r["p99_ms"]))
         rows.append(row)
     print(json.dumps({"metric": "served exact convolutions: p50/p99 latency across offered loads",
