@@ -104,17 +104,64 @@ __device__ __forceinline__ void spectral_block(const FT* F, double* v, const Dev
     }
 }
 
+// Inter-pass twiddle table of a length-L transform (PassTab layout: pass,
+// k, 17 entries per row; INV: of the inverse transform), filled cooperatively
+// by the workgroup; the caller synchronises before use.
+template <int L, class T, bool INV = false>
+__device__ __forceinline__ void fill_pass_tab(T* t, const DevPlan& p, int logn) {
+    using PT = PassTab<L>;
+    using B = Blk<L, 1, SEQ_FAST>;
+    const int lshift = logn - B::l;
+    const int nmask = (1 << logn) - 1;
+#pragma unroll
+    for (int q = 1; q < B::NP; ++q) {
+        const int cnt = 16 * PT::ns(q);
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const int k = e >> 4, r = e & 15;
+            const double2 w = p.P[tw_index<INV>(PT::expo(q, k, r), lshift, nmask)];
+            if constexpr (std::is_same<T, double2>::value) t[PT::off(q) + k * PT::ROW + r] = w;
+            else t[PT::off(q) + k * PT::ROW + r] = w.x;
+        }
+    }
+}
+
+// Inter-pass twiddles of a length-L transform from its shared pass table.
+template <class W, int L, class T>
+struct TwTab {
+    const T* t;
+    ModC M;
+    __device__ __forceinline__ void operator()(double* v, int p, int, int k) const {
+        const T* b = t + PassTab<L>::off(p) + PassTab<L>::ROW * k;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if constexpr (std::is_same<T, double2>::value) v[r] = W::mul_tw(v[r], b[r], M);
+            else v[r] = W::mul_w(v[r], b[r], M);
+        }
+    }
+};
+template <class W, int L, class T>
+__device__ __forceinline__ TwTab<W, L, T> twtab(const T* t, const ModC& M) {
+    return TwTab<W, L, T>{t, M};
+}
+
 // One tile of S convolutions of length L <= 2^12, entirely in the LDS of one
 // workgroup of S * max(1, L/16) threads: forward(f), forward(g), the product
 // with N^-1 folded in, inverse and the canonical store.  Item s of the tile
 // starts at offs[s] (offs != null) or at base + s L; items s >= cnt are
 // computed on item 0's data and not stored.
-template <class W, int L, int S, int OP = OP_MUL>
+//
+// TAB: the inter-pass twiddles come from `tab`, the workgroup's LDS table of
+// the forward transform (filled by the caller), and the inverse runs as the
+// forward transform of the spectrum with its index negated (x(t) = N^-1
+// F(X)(-t) = N^-1 F(X(-.))(t), Eq. 3 through Eq. 2), so one table serves all
+// three transforms.  Otherwise they are read from the global power table.
+template <class W, int L, int S, int OP = OP_MUL, bool TAB = false, class TE = double2>
 __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const typename W::word* g,
                                                 typename W::word* h, const uint64_t* offs, uint64_t base,
                                                 uint32_t cnt, const DevPlan& p, double* lds, int tid,
-                                                uint32_t* singular = nullptr) {
+                                                uint32_t* singular = nullptr, const TE* tab = nullptr) {
     using B = Blk<L, S, POS_FAST>;
+    static_assert(!TAB || B::NP > 1, "twiddle table: transforms with more than one pass");
     int s, j;
     B::item(tid, s, j);
     const bool valid = (uint32_t)s < cnt;
@@ -137,12 +184,17 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
 #pragma unroll
         for (int i = 0; i < B::E; ++i) gw[i] = g[off + B::pos0(j, i)];
     }
-    block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
+    auto forward = [&](double* vv) {
+        if constexpr (TAB) block_dft_tw<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M,
+                                                                  twtab<W, L>(tab, M));
+        else block_dft<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M);
+    };
+    forward(v);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) F[i] = W::to_s(v[i]);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(PRE_G ? gw[PRE_G ? i : 0] : g[off + B::pos0(j, i)], M);
-    block_dft<W, L, S, POS_FAST, false>(v, lds, s, j, p.P, lshift, p.nmask, M);
+    forward(v);
     // pointwise step with N^-1 folded in
     if constexpr (OP == OP_MUL) {
 #pragma unroll
@@ -150,17 +202,22 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
     } else {
         spectral_block<W, OP, B::E>(F, v, p, M, singular);
     }
-    if (B::R0 != B::RL) {
+    if (TAB || B::R0 != B::RL) {
         // output positions of the forward transform differ from the input
-        // positions of the inverse: reorder through LDS
+        // positions of the inverse (or, TAB, the spectrum is read at negated
+        // frequencies): reorder through LDS
 #pragma unroll
-        for (int i = 0; i < B::E; ++i) lds[B::lds(s, B::posL(j, i))] = v[i];
+        for (int i = 0; i < B::E; ++i) {
+            const int k = B::posL(j, i);
+            lds[B::lds(s, TAB ? ((L - k) & (L - 1)) : k)] = v[i];
+        }
         xch_sync<B::WAVE_LOCAL>();
 #pragma unroll
         for (int i = 0; i < B::E; ++i) v[i] = lds[B::lds(s, B::pos0(j, i))];
         xch_sync<B::WAVE_LOCAL>();
     }
-    block_dft<W, L, S, POS_FAST, true>(v, lds, s, j, p.P, lshift, p.nmask, M);
+    if constexpr (TAB) forward(v);
+    else block_dft<W, L, S, POS_FAST, true>(v, lds, s, j, p.P, lshift, p.nmask, M);
     if (valid) {
 #pragma unroll
         for (int i = 0; i < B::E; ++i) h[off + B::posL(j, i)] = W::canon(v[i], M);
@@ -171,6 +228,15 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
 // (<= 168 VGPRs) without spilling: measured 13% faster at 1024 than the
 // unconstrained allocation (two waves).  Longer tiles, 64-bit words and the
 // quotient (more registers) would spill there.
+// Tiles whose inter-pass twiddles sit in an LDS table (PassTab<L>) beside the
+// exchange buffer: (w, w/m) pairs while both fit half a CU's LDS, else w alone
+// (w/m formed at use).
+constexpr bool small_tab(int L) { return L >= 32 && L <= (1 << SMALL_MAX_LOG2N); }
+template <int L, int S>
+constexpr bool small_tab_pairs() {
+    return 8 * Blk<L, S, POS_FAST>::LDS_DOUBLES + 16 * PassTab<L>::SIZE <= 80 * 1024;
+}
+
 constexpr int small_waves_per_eu(int L, int op, int wb) { return (L <= 1024 && op == OP_MUL && wb == 4) ? 3 : 1; }
 
 template <class W, int L, int S, int OP>
@@ -181,8 +247,19 @@ __global__ __launch_bounds__(256, (small_waves_per_eu(L, OP, W::WB))) void k_con
     __shared__ double lds[Blk<L, S, POS_FAST>::LDS_DOUBLES];
     const uint64_t first = (uint64_t)blockIdx.x * S;
     const uint32_t cnt = (uint32_t)(count - first < (uint64_t)S ? count - first : (uint64_t)S);
-    small_conv_tile<W, L, S, OP>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds, threadIdx.x,
-                                 singular);
+    // (the one-wave tiles keep the global table: a table per 64 threads would
+    // cost more LDS, and more loads to fill, than it saves)
+    if constexpr (small_tab(L) && S == small_s(L)) {
+        using TE = typename std::conditional<small_tab_pairs<L, S>(), double2, double>::type;
+        __shared__ TE tab[PassTab<L>::SIZE];
+        fill_pass_tab<L>(tab, p, p.logn);
+        __syncthreads();
+        small_conv_tile<W, L, S, OP, true, TE>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds,
+                                               threadIdx.x, singular, tab);
+    } else {
+        small_conv_tile<W, L, S, OP>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds, threadIdx.x,
+                                     singular);
+    }
 }
 
 // MULIN (inverse only): the input is the pointwise product x y mod m, formed
@@ -206,7 +283,17 @@ __global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, ty
 #pragma unroll
         for (int i = 0; i < B::E; ++i) v[i] = W::mul_var(v[i], W::load_reduce(y[off + B::pos0(j, i)], M), M);
     }
-    block_dft<W, L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M);
+    // (one transform per tile: the table pays where it keeps three or more
+    // workgroups per CU; at 2048 and 4096 it measured even and 6-13% slower)
+    if constexpr (small_tab(L) && L <= 1024) {
+        using TE = typename std::conditional<small_tab_pairs<L, S>(), double2, double>::type;
+        __shared__ TE tab[PassTab<L>::SIZE];
+        fill_pass_tab<L, TE, INV>(tab, p, p.logn);
+        __syncthreads();
+        block_dft_tw<W, L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M, twtab<W, L>(tab, M));
+    } else {
+        block_dft<W, L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M);
+    }
     if (valid) {
 #pragma unroll
         for (int i = 0; i < B::E; ++i) {
@@ -357,23 +444,6 @@ struct FSLds {
     const Entry* rowf;
 };
 
-template <int L, class T>
-__device__ __forceinline__ void fill_pass_tab(T* t, const DevPlan& p, int logn) {
-    using PT = PassTab<L>;
-    using B = Blk<L, 1, SEQ_FAST>;
-    const int lshift = logn - B::l;
-    const int nmask = (1 << logn) - 1;
-#pragma unroll
-    for (int q = 1; q < B::NP; ++q) {
-        const int cnt = 16 * PT::ns(q);
-        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const int k = e >> 4, r = e & 15;
-            const double2 w = p.P[tw_index<false>(PT::expo(q, k, r), lshift, nmask)];
-            if constexpr (std::is_same<T, double2>::value) t[PT::off(q) + k * PT::ROW + r] = w;
-            else t[PT::off(q) + k * PT::ROW + r] = w.x;
-        }
-    }
-}
 
 // Where the exchange buffer and the twiddle tables sit in `lds`.
 template <int LOGN>
@@ -405,24 +475,6 @@ __device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p
     return L;
 }
 
-// Inter-pass twiddles of a length-L transform from its shared pass table.
-template <class W, int L, class T>
-struct TwTab {
-    const T* t;
-    ModC M;
-    __device__ __forceinline__ void operator()(double* v, int p, int, int k) const {
-        const T* b = t + PassTab<L>::off(p) + PassTab<L>::ROW * k;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if constexpr (std::is_same<T, double2>::value) v[r] = W::mul_tw(v[r], b[r], M);
-            else v[r] = W::mul_w(v[r], b[r], M);
-        }
-    }
-};
-template <class W, int L, class T>
-__device__ __forceinline__ TwTab<W, L, T> twtab(const T* t, const ModC& M) {
-    return TwTab<W, L, T>{t, M};
-}
 
 // Column phase, forward: length-B transforms of columns c0..c0+SC of x
 // (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
@@ -956,6 +1008,20 @@ struct MultiCfg {
     static constexpr int WORDS = mx(large_words<NMAX>(), SMALL_WORDS);
 };
 
+// The LDS twiddle table of a small tile of the multi-length kernel, after the
+// tile's exchange buffer in the space the long lengths size: (w, w/m) pairs
+// (MODE 2) or w alone (MODE 1) as they fit, else none (MODE 0: twiddles from
+// the global power table).
+template <class W, int K>
+struct MultiTab {
+    static constexpr int L = 1 << K;
+    static constexpr int OFF = (Blk<L, multi_s(L), POS_FAST>::LDS_DOUBLES + 1) & ~1;
+    static constexpr int FREE = MultiCfg<W>::WORDS - OFF;
+    static constexpr int TS = PassTab<L>::SIZE;
+    static constexpr int MODE = !small_tab(L) ? 0 : (2 * TS <= FREE ? 2 : (TS <= FREE ? 1 : 0));
+    using Entry = typename std::conditional<MODE == 2, double2, double>::type;
+};
+
 // Tasks of length 2^K, while the queue hands them out: the task list is
 // sorted longest first and tickets only grow, so a workgroup meets every
 // length at most once and in decreasing order.  Each length has its own loop
@@ -979,6 +1045,16 @@ __device__ __forceinline__ uint32_t multi_run(uint32_t t, const typename W::word
             t = __builtin_amdgcn_readfirstlane(queue_take(queue, ticket));
         } while (t < ntasks && tasks[t].logn == (uint32_t)K);
     } else {
+        constexpr int L = 1 << K, S = multi_s(L);
+        using MT = MultiTab<W, K>;
+        using TE = typename MT::Entry;
+        TE* tab = reinterpret_cast<TE*>(lds + MT::OFF);
+        if constexpr (MT::MODE != 0) {
+            // the previous class's waves may still read the table region
+            __syncthreads();
+            fill_pass_tab<L>(tab, p, K);
+            __syncthreads();
+        }
         do {
             const MultiTask task = tasks[t];
             // the thread index, opaque to the compiler on every pass, so that the
@@ -986,7 +1062,8 @@ __device__ __forceinline__ uint32_t multi_run(uint32_t t, const typename W::word
             // held in registers across the whole loop
             int tid = (int)threadIdx.x;
             asm volatile("" : "+v"(tid));
-            small_conv_tile<W, 1 << K, multi_s(1 << K)>(f, g, h, toffs + task.first, 0, task.cnt, p, lds, tid);
+            small_conv_tile<W, L, S, OP_MUL, MT::MODE != 0, TE>(f, g, h, toffs + task.first, 0, task.cnt, p, lds,
+                                                                tid, nullptr, tab);
             t = __builtin_amdgcn_readfirstlane(queue_take(queue, ticket));
         } while (t < ntasks && tasks[t].logn == (uint32_t)K);
     }
