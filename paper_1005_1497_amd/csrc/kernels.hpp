@@ -425,15 +425,26 @@ __device__ __forceinline__ void st_scr(const Buf& b, double y, uint32_t ve, uint
 // (w, w/m) pairs, which save the quotient multiply of every inter-pass
 // twiddle, unless the pairs would push the workgroup out of two-per-CU
 // residency or out of LDS; then they hold w alone and w/m is formed at use.
+//
+// PART selects what a kernel holds: FS_ALL (the fused kernels: both phases),
+// FS_COL (the column kernels of the multi-launch four-step: the column
+// exchange and table only) or FS_ROW (its row kernels: the row exchange and
+// table only), so that the column kernels of the long lengths fit two
+// workgroups per CU and no kernel fills a table it does not read.
 constexpr int LDS_HALF_CU = 80 * 1024;
-template <int LOGN>
+enum { FS_ALL = 0, FS_COL = 1, FS_ROW = 2 };
+template <int LOGN, int PART = FS_ALL>
 struct FSLds {
     using G = FS<LOGN>;
     static constexpr bool SAME = (G::A == G::Bn);
     static constexpr int TC = PassTab<G::Bn>::SIZE;   // entries per column table
     static constexpr int TR = PassTab<G::A>::SIZE;    // entries per row table
-    static constexpr int XCH2 = (G::XCH + 1) & ~1;     // tables start 16-byte aligned
-    static constexpr int ENTRIES = TC + (SAME ? 0 : TR);
+    static constexpr int XCHP = PART == FS_COL   ? G::BC::LDS_DOUBLES
+                                : PART == FS_ROW ? G::mx(G::BR::LDS_DOUBLES, G::BRS::LDS_DOUBLES)
+                                                 : G::XCH;
+    static constexpr int XCH2 = (XCHP + 1) & ~1;       // tables start 16-byte aligned
+    static constexpr bool HASC = PART != FS_ROW, HASR = PART != FS_COL && (PART == FS_ROW || !SAME);
+    static constexpr int ENTRIES = (HASC ? TC : 0) + (HASR ? TR : 0);
     static constexpr int BYTES1 = 8 * (XCH2 + ENTRIES);
     static constexpr int BYTES2 = 8 * (XCH2 + 2 * ENTRIES);
     static constexpr bool PAIRS = BYTES2 <= LDS_HALF_CU || (BYTES1 > LDS_HALF_CU && BYTES2 <= 150 * 1024);
@@ -446,31 +457,31 @@ struct FSLds {
 
 
 // Where the exchange buffer and the twiddle tables sit in `lds`.
-template <int LOGN>
-__device__ __forceinline__ FSLds<LOGN> fs_lds_layout(double* lds) {
-    using FL = FSLds<LOGN>;
+template <int LOGN, int PART = FS_ALL>
+__device__ __forceinline__ FSLds<LOGN, PART> fs_lds_layout(double* lds) {
+    using FL = FSLds<LOGN, PART>;
     FL L;
     L.xch = lds;
     typename FL::Entry* t = reinterpret_cast<typename FL::Entry*>(lds + FL::XCH2);
-    L.colf = t;
-    L.rowf = FL::SAME ? L.colf : t + FL::TC;
+    L.colf = FL::HASC ? t : nullptr;
+    L.rowf = PART == FS_ROW ? t : (PART == FS_COL ? nullptr : (FL::SAME ? t : t + FL::TC));
     return L;
 }
 
 // Fills the twiddle tables of plan p; ends with a barrier.
-template <int LOGN>
-__device__ __forceinline__ void fs_lds_fill(const FSLds<LOGN>& L, const DevPlan& p) {
+template <int LOGN, int PART>
+__device__ __forceinline__ void fs_lds_fill(const FSLds<LOGN, PART>& L, const DevPlan& p) {
     using G = FS<LOGN>;
-    using FL = FSLds<LOGN>;
+    using FL = FSLds<LOGN, PART>;
     using E = typename FL::Entry;
-    fill_pass_tab<G::Bn>(const_cast<E*>(L.colf), p, LOGN);
-    if (!FL::SAME) fill_pass_tab<G::A>(const_cast<E*>(L.rowf), p, LOGN);
+    if constexpr (FL::HASC) fill_pass_tab<G::Bn>(const_cast<E*>(L.colf), p, LOGN);
+    if constexpr (FL::HASR) fill_pass_tab<G::A>(const_cast<E*>(L.rowf), p, LOGN);
     __syncthreads();
 }
 
-template <int LOGN>
-__device__ __forceinline__ FSLds<LOGN> fs_lds_init(double* lds, const DevPlan& p) {
-    const FSLds<LOGN> L = fs_lds_layout<LOGN>(lds);
+template <int LOGN, int PART = FS_ALL>
+__device__ __forceinline__ FSLds<LOGN, PART> fs_lds_init(double* lds, const DevPlan& p) {
+    const FSLds<LOGN, PART> L = fs_lds_layout<LOGN, PART>(lds);
     fs_lds_fill<LOGN>(L, p);
     return L;
 }
@@ -503,9 +514,9 @@ __device__ __forceinline__ ColIn<W, LOGN> col_fwd_load(const typename W::word* x
 
 // Column phase, forward: length-B transforms of columns c0..c0+SC of x
 // (natural order), times w^(t1 u2), into scratch rows Y[u2 * A + t1].
-template <class W, int LOGN>
+template <class W, int LOGN, int PART>
 __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typename W::sword* Y, int c0,
-                                                const DevPlan& p, const FSLds<LOGN>& L) {
+                                                const DevPlan& p, const FSLds<LOGN, PART>& L) {
     using G = FS<LOGN>;
     using B = typename G::BC;
     int s, j;
@@ -527,9 +538,9 @@ __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typena
         st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), j * G::A + t1, B::posL(0, i) * G::A);
 }
 
-template <class W, int LOGN>
+template <class W, int LOGN, int PART>
 __device__ __forceinline__ void col_fwd_block(const typename W::word* x, typename W::sword* Y, int c0,
-                                              const DevPlan& p, const FSLds<LOGN>& L) {
+                                              const DevPlan& p, const FSLds<LOGN, PART>& L) {
     col_fwd_compute<W, LOGN>(col_fwd_load<W, LOGN>(x, c0), Y, c0, p, L);
 }
 
@@ -564,9 +575,9 @@ __device__ __forceinline__ RowIn<W, LOGN> row_conv_load(const typename W::sword*
 // independent work around each exchange, about 2% faster at 2^17..2^19, but
 // about 32 more VGPRs); the kernels limited to 128 VGPRs take them one after
 // the other.
-template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true>
+template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL>
 __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typename W::sword* Yf, int r0,
-                                                 const DevPlan& p, const FSLds<LOGN>& L,
+                                                 const DevPlan& p, const FSLds<LOGN, PART>& L,
                                                  uint32_t* singular = nullptr) {
     using G = FS<LOGN>;
     using B = typename G::BR;
@@ -621,9 +632,9 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i));
 }
 
-template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true>
+template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL>
 __device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const typename W::sword* Yg, int r0,
-                                               const DevPlan& p, const FSLds<LOGN>& L,
+                                               const DevPlan& p, const FSLds<LOGN, PART>& L,
                                                uint32_t* singular = nullptr) {
     row_conv_compute<W, LOGN, OP, LOCKSTEP>(row_conv_load<W, LOGN>(Yf, Yg, r0), Yf, r0, p, L, singular);
 }
@@ -687,9 +698,9 @@ struct NegStore {
     __device__ static constexpr uint32_t reg(int i) { return FS<LOGN>::A * FS<LOGN>::BC::posL(0, 15 - i); }
 };
 
-template <class W, int LOGN, bool SCALE, bool CRT = false>
+template <class W, int LOGN, bool SCALE, bool CRT = false, int PART = FS_ALL>
 __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typename W::word* x, int c0,
-                                                const DevPlan& p, const FSLds<LOGN>& L,
+                                                const DevPlan& p, const FSLds<LOGN, PART>& L,
                                                 const CrtStore& crt = CrtStore{}) {
     using G = FS<LOGN>;
     using B = typename G::BC;
@@ -744,16 +755,16 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
     }
 }
 
-template <class W, int LOGN, bool SCALE>
+template <class W, int LOGN, bool SCALE, int PART>
 __device__ __forceinline__ void col_inv_block(const typename W::sword* Y, typename W::word* x, int c0,
-                                              const DevPlan& p, const FSLds<LOGN>& L) {
+                                              const DevPlan& p, const FSLds<LOGN, PART>& L) {
     col_inv_compute<W, LOGN, SCALE>(col_inv_load<W, LOGN>(Y, c0), x, c0, p, L);
 }
 
 // Row phase of the natural-order forward transform: X[u2 + B u1].
-template <class W, int LOGN>
+template <class W, int LOGN, int PART>
 __device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, typename W::word* X, int r0,
-                                                  const DevPlan& p, const FSLds<LOGN>& L) {
+                                                  const DevPlan& p, const FSLds<LOGN, PART>& L) {
     using G = FS<LOGN>;
     using B = typename G::BRS;
     int s, j;
@@ -773,9 +784,9 @@ __device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, ty
 // Row phase of the natural-order inverse transform: from X[u2 + B u1] to
 // scratch rows: forward row transforms times w^(u2 s1) (the inverse column
 // phase negates the output index).
-template <class W, int LOGN>
+template <class W, int LOGN, int PART>
 __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typename W::sword* Y, int r0,
-                                                  const DevPlan& p, const FSLds<LOGN>& L) {
+                                                  const DevPlan& p, const FSLds<LOGN, PART>& L) {
     using G = FS<LOGN>;
     using B = typename G::BRS;
     int s, j;
@@ -799,8 +810,8 @@ __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typ
 template <class W, int LOGN>
 __global__ __launch_bounds__(512) void k_fs_col_fwd(const typename W::word* x, typename W::sword* Y,
                                                     uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_COL>::WORDS];
+    const FSLds<LOGN, FS_COL> L = fs_lds_init<LOGN, FS_COL>(lds, p);
     col_fwd_block<W, LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
 }
 // Column phase of both operands in one launch: grid.y = 2 * items, the first
@@ -809,8 +820,8 @@ template <class W, int LOGN>
 __global__ __launch_bounds__(512) void k_fs_col_fwd2(const typename W::word* f, const typename W::word* g,
                                                      typename W::sword* Y, uint64_t item_stride, uint64_t ystride,
                                                      uint32_t items, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_COL>::WORDS];
+    const FSLds<LOGN, FS_COL> L = fs_lds_init<LOGN, FS_COL>(lds, p);
     const uint32_t second = blockIdx.y >= items ? 1u : 0u;
     const uint32_t item = blockIdx.y - second * items;
     col_fwd_block<W, LOGN>((second ? g : f) + item * item_stride, Y + item * ystride + second * FS<LOGN>::N,
@@ -819,32 +830,32 @@ __global__ __launch_bounds__(512) void k_fs_col_fwd2(const typename W::word* f, 
 template <class W, int LOGN, int OP>
 __global__ __launch_bounds__(512) void k_fs_row_conv(typename W::sword* Yf, const typename W::sword* Yg,
                                                      uint64_t ystride, DevPlan p, uint32_t* singular) {
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_ROW>::WORDS];
+    const FSLds<LOGN, FS_ROW> L = fs_lds_init<LOGN, FS_ROW>(lds, p);
     row_conv_block<W, LOGN, OP>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR,
                                 p, L, singular);
 }
 template <class W, int LOGN, bool SCALE>
 __global__ __launch_bounds__(512) void k_fs_col_inv(const typename W::sword* Y, typename W::word* x,
                                                     uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_COL>::WORDS];
+    const FSLds<LOGN, FS_COL> L = fs_lds_init<LOGN, FS_COL>(lds, p);
     col_inv_block<W, LOGN, SCALE>(Y + blockIdx.y * ystride, x + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SC,
                                   p, L);
 }
 template <class W, int LOGN>
 __global__ __launch_bounds__(512) void k_fs_row_fwd_nat(const typename W::sword* Y, typename W::word* X,
                                                         uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_ROW>::WORDS];
+    const FSLds<LOGN, FS_ROW> L = fs_lds_init<LOGN, FS_ROW>(lds, p);
     row_fwd_nat_block<W, LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SR, p,
                                L);
 }
 template <class W, int LOGN>
 __global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* X, typename W::sword* Y,
                                                         uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN>::WORDS];
-    const FSLds<LOGN> L = fs_lds_init<LOGN>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_ROW>::WORDS];
+    const FSLds<LOGN, FS_ROW> L = fs_lds_init<LOGN, FS_ROW>(lds, p);
     row_inv_nat_block<W, LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SR, p,
                                L);
 }
@@ -893,10 +904,10 @@ __device__ __forceinline__ void queue_leave(uint32_t* q) {
 // registers): bit 0 the forward columns, bit 1 the rows, bit 2 the inverse
 // columns; bit 3 transforms the f and g rows pass by pass together
 // (row_conv_compute's LOCKSTEP).  Ends with a barrier.
-template <class W, int LOGN, int PF, int OP = OP_MUL>
+template <class W, int LOGN, int PF, int OP = OP_MUL, int PART = FS_ALL>
 __device__ __forceinline__ void fused_conv_item(const typename W::word* fi, const typename W::word* gi,
                                                 typename W::word* hi, typename W::sword* Yf,
-                                                typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN>& L,
+                                                typename W::sword* Yg, const DevPlan& p, const FSLds<LOGN, PART>& L,
                                                 uint32_t* singular = nullptr, const CrtStore& crt = CrtStore{}) {
     using G = FS<LOGN>;
     constexpr int CL = G::A - G::SC;
