@@ -3,6 +3,20 @@
 
 namespace nttmi {
 
+// Workgroups per item of a row kernel.  Rows of 2^loop_la positions and more
+// (the kernel's threshold, FS_ROW_LOOP_*): fewer workgroups than row blocks
+// once the batch has many, each taking several blocks and filling its twiddle
+// table once for them, with at least about 1024 workgroups in the launch.
+// Shorter rows keep a workgroup per block.
+static uint32_t fs_row_grid(int la, int loop_la, uint32_t rblocks, uint32_t items) {
+    if (la < loop_la) return rblocks;
+    const uint64_t total = (uint64_t)rblocks * items;
+    uint32_t per = (uint32_t)(total / 1024);   // blocks per workgroup
+    if (per < 1) per = 1;
+    if (per > rblocks) per = rblocks;
+    return (rblocks + per - 1) / per;
+}
+
 template <class W>
 static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* h, uint32_t items,
                                   uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
@@ -26,10 +40,14 @@ static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* 
                                Yg, item_stride, ys, p);                                                           \
         }                                                                                                         \
         if (singular)                                                                                             \
-            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_DIV>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
+            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_DIV>),                                                     \
+                               dim3(fs_row_grid(G::la, FS_ROW_LOOP_CONV, G::Bn / G::SR, items), items),           \
+                               dim3(G::T), 0, st, Yf,                                                             \
                                (const SW*)Yg, ys, p, singular);                                                   \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_MUL>), dim3(G::Bn / G::SR, items), dim3(G::T), 0, st, Yf,  \
+            hipLaunchKernelGGL((k_fs_row_conv<W, n, OP_MUL>),                                                     \
+                               dim3(fs_row_grid(G::la, FS_ROW_LOOP_CONV, G::Bn / G::SR, items), items),           \
+                               dim3(G::T), 0, st, Yf,                                                             \
                                (const SW*)Yg, ys, p, singular);                                                   \
         hipLaunchKernelGGL((k_fs_col_inv<W, n, false>), dim3(G::A / G::SC, items), dim3(G::T), 0, st,              \
                            (const SW*)Yf, (T*)h, item_stride, ys, p);                                             \
@@ -63,10 +81,14 @@ static hipError_t ntt_fourstep_t(int logn, bool inv, const void* x, void* X, uin
         if (!inv) {                                                                                               \
             hipLaunchKernelGGL((k_fs_col_fwd<W, n>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st, (const T*)x,   \
                                (SW*)scratch, N, N, p);                                                            \
-            hipLaunchKernelGGL((k_fs_row_fwd_nat<W, n>), dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,           \
+            hipLaunchKernelGGL((k_fs_row_fwd_nat<W, n>),                                                          \
+                               dim3(fs_row_grid(G::la, FS_ROW_LOOP_NAT, G::Bn / G::SR, batch), batch),            \
+                               dim3(G::T), 0, st,                                                                 \
                                (const SW*)scratch, (T*)X, N, N, p);                                               \
         } else {                                                                                                  \
-            hipLaunchKernelGGL((k_fs_row_inv_nat<W, n>), dim3(G::Bn / G::SR, batch), dim3(G::T), 0, st,           \
+            hipLaunchKernelGGL((k_fs_row_inv_nat<W, n>),                                                          \
+                               dim3(fs_row_grid(G::la, FS_ROW_LOOP_NAT, G::Bn / G::SR, batch), batch),            \
+                               dim3(G::T), 0, st,                                                                 \
                                (const T*)x, (SW*)scratch, N, N, p);                                               \
             hipLaunchKernelGGL((k_fs_col_inv<W, n, true>), dim3(G::A / G::SC, batch), dim3(G::T), 0, st,          \
                                (const SW*)scratch, (T*)X, N, N, p);                                               \
