@@ -305,15 +305,31 @@ def main():
         torch.cuda.synchronize()
         greps = max(args.steps, 5)
         gevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(greps)]
+        eevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(greps)]
         with torch.cuda.stream(gs):                          # replay() launches on the current stream
-            for a, b in gevs:
+            # warm-up replays (the first replay uploads the graph) and eager
+            # launches on the same stream, so that both are timed after the
+            # per-item form's small launches at the same clock
+            for _ in range(max(args.warmup // 5, 5)):
+                graph.replay()
+                nt.conv_batched(f, g, desc, m, out=h, stream=gs)
+            for (a, b), (c, d) in zip(gevs, eevs):
                 a.record(gs)
                 graph.replay()
                 b.record(gs)
+                c.record(gs)
+                nt.conv_batched(f, g, desc, m, out=h, stream=gs)
+                d.record(gs)
         torch.cuda.synchronize()
         gper = np.array([a.elapsed_time(b) for a, b in gevs])
+        eper = np.array([a.elapsed_time(b) for a, b in eevs])
         forms["graph_replay_ms_per_step"] = float(gper.mean())
         forms["graph_replay_conv_per_s"] = COUNT / (gper.mean() / 1e3)
+        forms["eager_interleaved_ms_per_step"] = float(eper.mean())
+        with torch.cuda.stream(gs):                          # the replay alone writes h
+            h.zero_()
+            graph.replay()
+        torch.cuda.synchronize()
         gok = bool(np.array_equal(h.cpu().numpy().view(np.uint32), hh))
         forms["graph_replay_matches_eager"] = gok
         if not gok:
