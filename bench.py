@@ -204,6 +204,10 @@ def main():
                     help="lengths: the log2 N of the uniform 2^26-element batches")
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     ap.add_argument("--rhos", default="0.3,0.5,0.7,0.9", help="serve-sweep: the offered loads")
+    ap.add_argument("--streams", type=int, default=4, help="serve-sweep: streams of the native scheduler")
+    ap.add_argument("--inflight", type=int, default=4, help="serve-sweep: batches in flight (native scheduler)")
+    ap.add_argument("--solo", type=int, default=16,
+                    help="serve-sweep: requests of 2^SOLO words and more run as batches of their own (0: never)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 4 times (reference kernel for the HBM byte counters)")
     ap.add_argument("--traffic-from", metavar="DIR",
@@ -817,8 +821,9 @@ def serve_sweep(args):
     rhos = [float(x) for x in args.rhos.split(",")]
 
     def native(rate, max_batch=512):
-        srv = sv.NativeConvServer(m, capacity_log2=cap, elem_bits=64, streams=4, max_batch=max_batch,
-                                  max_batch_elems=1 << (cap - 2), max_inflight=4)
+        srv = sv.NativeConvServer(m, capacity_log2=cap, elem_bits=64, streams=args.streams, max_batch=max_batch,
+                                  max_batch_elems=1 << (cap - 2), max_inflight=args.inflight,
+                                  solo_log2n=args.solo)
         for t in [srv.submit(f, g) for f, g in reqs[:warm]]:
             srv.result(t)
         srv.stats(reset=True)
@@ -906,7 +911,8 @@ def serve_sweep(args):
     print(json.dumps({"metric": "served exact convolutions: p50/p99 latency across offered loads",
                       "unit": "ms", "n_gpus": 1, "requests": n, "warmup": warm, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "words": "u64",
-                                 "scheduler": "native (ntt_server_*)", "streams": 4,
+                                 "scheduler": "native (ntt_server_*)", "streams": args.streams,
+                                 "max_inflight": args.inflight, "solo_log2n": args.solo,
                                  "max_batch_elems": 1 << (cap - 2)},
                       "saturated": sat, "one_launch_per_request_saturated": single_sat, "sweep": rows}), flush=True)
 

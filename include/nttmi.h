@@ -309,6 +309,15 @@ ntt_status ntt_server_wait(ntt_server *srv, uint64_t ticket, void *h, double tim
 ntt_status ntt_server_stats(ntt_server *srv, uint64_t *completed, double *mean_batch, double *p50_ms,
                             double *p99_ms, uint32_t reset);
 
+/* Admission policy: requests of 2^solo_log2n words and more are launched as
+ * batches of their own, never together with other requests (0: no such
+ * limit; the default is 16).  In a batch with other items a long convolution
+ * runs on a single workgroup and every request of that batch completes only
+ * with it; alone it takes the four-step form, whose phases spread over the
+ * chip.  Applies to requests admitted after the call.  NTT_E_ARG: null
+ * server. */
+ntt_status ntt_server_set_solo(ntt_server *srv, uint32_t solo_log2n);
+
 /* Finishes every queued and running request, stops the thread and frees the
  * server.  Tickets not yet waited for are released.  No other call on the
  * server may run concurrently with it or follow it.  The other ntt_server_*

@@ -111,6 +111,8 @@ def _load():
     L.ntt_server_stats.argtypes = [VP, ctypes.POINTER(U64), ctypes.POINTER(D), ctypes.POINTER(D),
                                    ctypes.POINTER(D), U32]
     L.ntt_server_stats.restype = I32
+    L.ntt_server_set_solo.argtypes = [VP, U32]
+    L.ntt_server_set_solo.restype = I32
     L.ntt_server_destroy.argtypes = [VP]
     L.ntt_server_destroy.restype = None
     L.ntt_status_string.argtypes = [I32]

@@ -124,6 +124,11 @@ struct ntt_server {
     uint32_t rlo = 0, bits = 0, arena_log2 = 0;
     uint32_t max_batch = 1, max_inflight = 1;
     uint64_t max_batch_elems = 0;
+    // requests of 2^solo_log2n words and more run as batches of their own (0:
+    // never).  In a batch with other items a long convolution runs on one
+    // workgroup and every request of the batch completes with it; alone it
+    // takes the four-step form spread over the chip.
+    uint32_t solo_log2n = 16;
     size_t wb = 4;
     int dev = 0;
     char *F = nullptr, *G = nullptr, *H = nullptr;
@@ -214,7 +219,8 @@ void ntt_server::run() {
             while (!queue.empty() && adm.size() < max_batch) {
                 Req* r = queue.front();
                 const uint64_t size = 1ull << r->log2n;
-                if (!adm.empty() && elems + size > max_batch_elems) break;
+                const bool solo = solo_log2n != 0 && r->log2n >= solo_log2n;
+                if (!adm.empty() && (solo || elems + size > max_batch_elems)) break;
                 uint64_t o = 0;
                 if (!buddy.alloc((int)r->log2n, &o)) break;
                 queue.pop_front();
@@ -222,6 +228,7 @@ void ntt_server::run() {
                 r->state = Q_RUNNING;
                 elems += size;
                 adm.push_back(r);
+                if (solo) break;
             }
         }
         bool progress = false;
@@ -446,6 +453,13 @@ ntt_status ntt_server_stats(ntt_server* s, uint64_t* completed, double* mean_bat
         s->batches = 0;
         s->batched_reqs = 0;
     }
+    return NTT_OK;
+}
+
+ntt_status ntt_server_set_solo(ntt_server* s, uint32_t solo_log2n) {
+    if (!s) return NTT_E_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->solo_log2n = solo_log2n;
     return NTT_OK;
 }
 

@@ -407,7 +407,8 @@ class NativeConvServer:
     released during the call) and returns a ticket; result() waits for it."""
 
     def __init__(self, m: int, capacity_log2: int, elem_bits: int = 64, streams: int = 4, max_batch: int = 512,
-                 max_batch_elems: int = 0, max_inflight: int = 4, root: int = 2, root_log2order: int | None = None):
+                 max_batch_elems: int = 0, max_inflight: int = 4, root: int = 2, root_log2order: int | None = None,
+                 solo_log2n: int | None = None):
         import ctypes
         import paper_1005_1497_amd as nt
         self._nt, self._ct = nt, ctypes
@@ -417,6 +418,8 @@ class NativeConvServer:
         nt._check(nt.lib.ntt_server_create(m, root, rlo, elem_bits, capacity_log2, streams, max_batch,
                                             max_batch_elems, max_inflight, ctypes.byref(h)), "ntt_server_create")
         self._h = h
+        if solo_log2n is not None:   # else the library's default (2^16 words and more run alone)
+            nt._check(nt.lib.ntt_server_set_solo(h, int(solo_log2n)), "ntt_server_set_solo")
 
     def submit(self, f: np.ndarray, g: np.ndarray) -> int:
         f = np.ascontiguousarray(f, dtype=self.np_dtype)

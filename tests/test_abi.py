@@ -59,6 +59,8 @@ def lib():
     L.ntt_server_wait.restype = I32
     L.ntt_server_stats.argtypes = [VP, VP, VP, VP, VP, U32]
     L.ntt_server_stats.restype = I32
+    L.ntt_server_set_solo.argtypes = [VP, U32]
+    L.ntt_server_set_solo.restype = I32
     L.ntt_server_destroy.argtypes = [VP]
     L.ntt_server_destroy.restype = None
     L.ntt_status_string.argtypes = [I32]
@@ -230,6 +232,7 @@ def test_server_argument_validation(lib):
     assert lib.ntt_server_submit(None, None, None, 4, ctypes.byref(t)) == 1
     assert lib.ntt_server_wait(None, 1, None, 0.0) == 1
     assert lib.ntt_server_stage(None, 4, None, None, None) == 1
+    assert lib.ntt_server_set_solo(None, 16) == 1
     assert lib.ntt_server_submit_staged(None, 1) == 1
     assert lib.ntt_server_stats(None, None, None, None, None, 0) == 1
     lib.ntt_server_destroy(None)

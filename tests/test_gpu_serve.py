@@ -74,8 +74,11 @@ def test_zero_copy_submission_and_result_lifetime():
         assert np.array_equal(fu.result(), host(nt.conv_circular(dev(f), dev(g), m)))
 
 
+@pytest.mark.parametrize("solo", [None, 0])
 @pytest.mark.parametrize("bits,m", [(64, si.M_U64), (32, si.M_13631489)])
-def test_native_server_equals_alone(bits, m):
+def test_native_server_equals_alone(bits, m, solo):
+    # solo None: the default admission (requests of 2^16 words and more run as
+    # batches of their own); 0: every length may share a batch
     # the library's own scheduler thread: every result equals the request run
     # alone; two client threads submit at once; the oracle checks a few
     # entries.  Operands are staged first and the threads only queue them, so
@@ -89,7 +92,8 @@ def test_native_server_equals_alone(bits, m):
     lens = si.served_lengths(200, seed=6) if bits == 64 else rng.integers(4, 16, 200)
     dt = np.uint64 if bits == 64 else np.uint32
     reqs = [(rng.integers(0, m, 1 << int(n), dtype=dt), rng.integers(0, m, 1 << int(n), dtype=dt)) for n in lens]
-    with NativeConvServer(m, capacity_log2=21, elem_bits=bits, streams=4, max_batch_elems=1 << 19) as srv:
+    with NativeConvServer(m, capacity_log2=21, elem_bits=bits, streams=4, max_batch_elems=1 << 19,
+                          solo_log2n=solo) as srv:
         tickets = []
         for f, g in reqs:
             bf, bg, t = srv.stage(f.size)
