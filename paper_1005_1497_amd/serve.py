@@ -229,16 +229,20 @@ class ConvServer:
     """Continuous-batching server over an executor (see module docstring)."""
 
     def __init__(self, executor, capacity_log2: int, min_log2: int = 0, max_batch: int = 512,
-                 max_inflight: int = 4, max_batch_elems: int | None = None):
+                 max_inflight: int = 4, max_batch_elems: int | None = None, solo_log2n: int = 16):
         """max_batch caps the requests of one launch; max_batch_elems caps its
         arena elements (a single larger request still goes alone), so that
         several batches fit in the arena at once and the uploads of one
-        overlap the work of another."""
+        overlap the work of another.  Requests of 2^solo_log2n words and more
+        run as batches of their own (0: never), as in the native scheduler: in
+        a batch with other items a long convolution runs on one workgroup and
+        the whole batch completes with it."""
         self.ex = executor
         self.alloc = BuddyAllocator(capacity_log2, min_log2)
         self.max_batch = max_batch
         self.max_batch_elems = max_batch_elems
         self.max_inflight = max_inflight
+        self.solo_log2n = solo_log2n
         self.queue = collections.deque()
         self.inflight = []
         self.stats = ServeStats()
@@ -338,7 +342,8 @@ class ConvServer:
         while self.queue and len(admitted) < self.max_batch:
             r = self.queue[0]
             size = 1 << max(r.log2n, self.alloc.min_log2)
-            if admitted and self.max_batch_elems is not None and elems + size > self.max_batch_elems:
+            solo = self.solo_log2n != 0 and r.log2n >= self.solo_log2n
+            if admitted and (solo or (self.max_batch_elems is not None and elems + size > self.max_batch_elems)):
                 break
             off = self.alloc.alloc(r.log2n)
             if off is None:
@@ -348,6 +353,8 @@ class ConvServer:
             elems += size
             admitted.append(r)
             self.admission_log.append(r.rid)
+            if solo:
+                break
         self.stats.peak_used = max(self.stats.peak_used, self.alloc.used)
         return admitted
 

@@ -207,3 +207,29 @@ def test_batch_element_cap():
     assert [r for b in ex.launches for r in b] == list(range(60))     # arrival order kept
     for (f, g), fu in zip(reqs, futs):
         assert np.array_equal(fu.result(), oracle.conv_direct(f, g, M))
+
+
+def test_long_requests_run_alone():
+    # requests of 2^solo_log2n words and more close the batch being formed and
+    # run as batches of their own; arrival order is kept
+    ex = FakeExecutor(M, delay=0.001)
+    srv = ConvServer(ex, capacity_log2=12, max_inflight=1, solo_log2n=6)
+    rng = np.random.default_rng(9)
+    sizes = [3, 6, 3, 3, 7, 3]
+    reqs = [(rng.integers(0, M, 1 << k, dtype=np.uint64), rng.integers(0, M, 1 << k, dtype=np.uint64)) for k in sizes]
+    futs = [srv.submit(f, g) for f, g in reqs]   # all queued before the first admission
+    srv.start()
+    srv.drain()
+    srv.stop()
+    assert ex.launches == [[0], [1], [2, 3], [4], [5]]
+    for (f, g), fu in zip(reqs, futs):
+        assert np.array_equal(fu.result(), oracle.conv_direct(f, g, M))
+    # with the limit off every length shares a batch
+    ex0 = FakeExecutor(M, delay=0.001)
+    srv0 = ConvServer(ex0, capacity_log2=12, max_inflight=1, solo_log2n=0)
+    for f, g in reqs:
+        srv0.submit(f, g)
+    srv0.start()
+    srv0.drain()
+    srv0.stop()
+    assert ex0.launches == [[0, 1, 2, 3, 4, 5]]
