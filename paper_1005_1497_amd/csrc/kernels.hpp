@@ -544,6 +544,20 @@ __device__ __forceinline__ void col_fwd_block(const typename W::word* x, typenam
     col_fwd_compute<W, LOGN>(col_fwd_load<W, LOGN>(x, c0), Y, c0, p, L);
 }
 
+// Where the row phases of the inverse store: row position s1 of row u2 goes to
+// scratch column (s1 - 1) mod A, so that the inverse column phase, which needs
+// column -d mod A for destination column d, finds it at A - 1 - d and reads
+// whole cache lines (see col_inv_src).  Positions s1 = j + posL(0, i) with
+// posL(0, i) = i A / 16: registers i >= 1 keep the per-lane offset u2 A + j and
+// take the uniform offset posL(0, i) - 1; register 0 takes the per-lane offset
+// below (lane j = 0, position 0, goes to the row's last column).  No offset is
+// negative, so the buffer's range check drops nothing.
+template <int LOGN>
+__device__ __forceinline__ uint32_t scr_row_shift(int u2, int j) {
+    using G = FS<LOGN>;
+    return (uint32_t)(u2 * G::A + (j == 0 ? G::A : j) - 1);
+}
+
 // Row phase of a convolution: for rows r0..r0+SR, forward(f row), forward(g
 // row), product with N^-1, then the first half of the inverse four-step as a
 // forward one (row transforms, times w^(t1 u2)), back into Yf; the inverse
@@ -628,8 +642,10 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     // inverse column phase), then the twiddle w^(u2 s1) of the forward four-step
     block_dft_tw<W, G::A, G::SR, POS_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
                                                   twtab<W, G::A>(L.rowf, M));
+    // scratch column (s1 - 1) mod A for row position s1 (scr_row_shift)
+    st_scr<W>(bf, W::mul_w(v[0], (double)tw4[0], M), scr_row_shift<LOGN>(u2, j), 0u);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i));
+    for (int i = 1; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i) - 1);
 }
 
 template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL>
@@ -643,8 +659,10 @@ __device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const type
 // N^-1, canonical store.  Each transform is the forward one and its output
 // index is negated (Eq. 3 as the forward transform of Eq. 2 read at -t), so
 // the block that stores destination columns c0 .. c0 + SC - 1 transforms the
-// source columns t1 = -(c0 + s) mod A: the SC columns ending at A - c0, taken
-// in ascending order, one of them (the last, A - c0 = A) wrapping to column 0.
+// columns t1 = -(c0 + s) mod A.  The row phases store column t1 at scratch
+// position (t1 - 1) mod A (scr_row_shift), so those columns sit at positions
+// A - 1 - (c0 + s): the SC positions ending at A - 1 - c0, one whole block of
+// cache lines, read in ascending order.
 template <class W, int LOGN>
 struct ColInvIn {
     typename W::sword w[FS<LOGN>::BC::E];
@@ -653,7 +671,7 @@ struct ColInvIn {
 template <int LOGN>
 __device__ __forceinline__ uint32_t col_inv_src(int c0, int s) {
     using G = FS<LOGN>;
-    return (uint32_t)(G::A - c0 - (G::SC - 1) + s) & (uint32_t)(G::A - 1);
+    return (uint32_t)(G::A - c0 - G::SC + s);
 }
 
 template <class W, int LOGN>
@@ -802,8 +820,10 @@ __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typ
     for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, u2 * G::A + j, B::posL(0, i));
     block_dft_tw<W, G::A, G::SR, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::lb, G::N - 1, M,
                                                   twtab<W, G::A>(L.rowf, M));
+    st_scr<W>(by, W::mul_w(v[0], (double)tw4[0], M), scr_row_shift<LOGN>(u2, j), 0u);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), u2 * G::A + j, B::posL(0, i));
+    for (int i = 1; i < B::E; ++i)
+        st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), u2 * G::A + j, B::posL(0, i) - 1);
 }
 
 // Kernels of the multi-launch four-step (grid.y = item / row of the batch).
