@@ -134,6 +134,9 @@ struct ntt_server {
     char *F = nullptr, *G = nullptr, *H = nullptr;
     std::vector<hipStream_t> streams;
     size_t next_stream = 0;
+    // completed batches' events, reused by later batches (touched by the
+    // scheduler thread only, and by destroy after it has stopped)
+    std::vector<hipEvent_t> free_events;
     Buddy buddy{0};
     PinnedPool pool;
 
@@ -191,7 +194,14 @@ bool ntt_server::launch(std::vector<Req*>& adm) {
         e = hipMemcpyAsync(r->staging + 2 * row, H + r->off * wb, row, hipMemcpyDeviceToHost, s);
     }
     Batch b;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        if (!free_events.empty()) {
+            b.ev = free_events.back();
+            free_events.pop_back();
+        } else {
+            e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+        }
+    }
     if (e == hipSuccess) e = hipEventRecord(b.ev, s);
     if (e != hipSuccess) {
         // the stream may still run what was enqueued: let it finish first
@@ -258,7 +268,8 @@ void ntt_server::run() {
                 r->state = q == hipSuccess ? Q_DONE : Q_FAILED;
                 if (q == hipSuccess) record_latency(std::chrono::duration<double, std::milli>(now - r->arrival).count());
             }
-            (void)hipEventDestroy(inflight[i].ev);
+            if (q == hipSuccess) free_events.push_back(inflight[i].ev);
+            else (void)hipEventDestroy(inflight[i].ev);
             inflight.erase(inflight.begin() + (long)i);
             progress = true;
         }
@@ -475,6 +486,7 @@ void ntt_server_destroy(ntt_server* s) {
         s->pool.put(kv.second->staging, kv.second->staging_bytes);
         delete kv.second;
     }
+    for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
     for (hipStream_t h : s->streams) {
         nttmi::release_stream_caches(h);
         (void)hipStreamDestroy(h);
