@@ -903,7 +903,7 @@ __global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* 
 template <class W, int LOGN, int OP = OP_MUL>
 struct FusedCfg {
     // (the deconvolution's simultaneous inversion needs more registers)
-    static constexpr bool TWO = (W::WB == 4) && LOGN >= 14 && LOGN <= 16 && OP != OP_DIV;
+    static constexpr bool TWO = (W::WB == 4) && LOGN >= 13 && LOGN <= 16 && OP != OP_DIV;
     // minimum waves per SIMD (the second __launch_bounds__ argument): four
     // for two 512-thread workgroups per CU, i.e. at most 128 VGPRs
     static constexpr int WAVES_PER_EU = TWO ? 4 : 2;
