@@ -144,6 +144,77 @@ __device__ __forceinline__ TwTab<W, L, T> twtab(const T* t, const ModC& M) {
     return TwTab<W, L, T>{t, M};
 }
 
+// Tiles whose inter-pass twiddles sit in an LDS table (PassTab<L>) beside the
+// exchange buffer: (w, w/m) pairs while both fit half a CU's LDS, else w alone
+// (w/m formed at use).
+constexpr bool small_tab(int L) { return L >= 32 && L <= (1 << SMALL_MAX_LOG2N); }
+// 256-thread tiles whose table is split (SplitTab): the full table keeps them at
+// two workgroups per CU (72 KB), the split one at three (41-44 KB).  Measured
+// on 2^26-element batches: convolutions at 2048 and 4096 0.427 -> 0.369 ms (64-bit
+// words 0.322 -> 0.297), transforms 0.220-0.239 -> 0.182-0.184 ms forward; at 1024
+// the split table gained nothing (its full table already leaves three per CU).
+constexpr bool small_split(int L) { return L >= 2048 && L <= (1 << SMALL_MAX_LOG2N); }
+
+// Split twiddle table of a length-L transform with three passes (L >= 512):
+// pass 1's table as in PassTab, then for the last pass (Ns = ns(2)) a 16 x 17
+// table of w_{16 Ns}^(r kl), kl < 16, instead of its Ns x 17 one.  The last
+// pass's twiddle for k = 16 kh + kl is pass 1's entry (kh, r) = w_Ns^(r kh)
+// times the small table's (kl, r): one product more per twiddle, and a table of
+// 544 instead of 4624 entries at 4096 (8.7 instead of 74 KB of pairs).
+template <int L>
+struct SplitTab {
+    using PT = PassTab<L>;
+    static constexpr int LAST = Blk<L, 1, SEQ_FAST>::NP - 1;
+    static_assert(LAST == 2, "split table: transforms of three passes");
+    static constexpr int LO = PT::off(LAST);   // where the small table starts
+    static constexpr int SIZE = LO + PT::ROW * 16;
+};
+
+template <int L, class T, bool INV = false>
+__device__ __forceinline__ void fill_split_tab(T* t, const DevPlan& p, int logn) {
+    using PT = PassTab<L>;
+    using ST = SplitTab<L>;
+    const int lshift = logn - Blk<L, 1, SEQ_FAST>::l;
+    const int nmask = (1 << logn) - 1;
+    for (int e = threadIdx.x; e < 16 * PT::ns(1) + 256; e += blockDim.x) {
+        const bool lo = e >= 16 * PT::ns(1);
+        const int f = lo ? e - 16 * PT::ns(1) : e;
+        const int k = f >> 4, r = f & 15;
+        const double2 w = p.P[tw_index<INV>(PT::expo(lo ? ST::LAST : 1, k, r), lshift, nmask)];
+        T* d = t + (lo ? ST::LO : PT::off(1)) + k * PT::ROW + r;
+        if constexpr (std::is_same<T, double2>::value) *d = w;
+        else *d = w.x;
+    }
+}
+
+template <class W, int L, class T>
+struct TwSplit {
+    const T* t;
+    ModC M;
+    __device__ __forceinline__ void operator()(double* v, int p, int, int k) const {
+        using PT = PassTab<L>;
+        using ST = SplitTab<L>;
+        if (p < ST::LAST) {
+            const T* b = t + PT::off(p) + PT::ROW * k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if constexpr (std::is_same<T, double2>::value) v[r] = W::mul_tw(v[r], b[r], M);
+                else v[r] = W::mul_w(v[r], b[r], M);
+            }
+        } else {
+            const T* bh = t + PT::off(ST::LAST - 1) + PT::ROW * (k >> 4);
+            const T* bl = t + ST::LO + PT::ROW * (k & 15);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                double w;
+                if constexpr (std::is_same<T, double2>::value) w = W::mul_tw(bh[r].x, bl[r], M);
+                else w = W::mul_w(bh[r], bl[r], M);
+                v[r] = W::mul_w(v[r], w, M);
+            }
+        }
+    }
+};
+
 // One tile of S convolutions of length L <= 2^12, entirely in the LDS of one
 // workgroup of S * max(1, L/16) threads: forward(f), forward(g), the product
 // with N^-1 folded in, inverse and the canonical store.  Item s of the tile
@@ -185,9 +256,12 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
         for (int i = 0; i < B::E; ++i) gw[i] = g[off + B::pos0(j, i)];
     }
     auto forward = [&](double* vv) {
-        if constexpr (TAB) block_dft_tw<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M,
-                                                                  twtab<W, L>(tab, M));
-        else block_dft<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M);
+        if constexpr (TAB && small_split(L))
+            block_dft_tw<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M, TwSplit<W, L, TE>{tab, M});
+        else if constexpr (TAB)
+            block_dft_tw<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M, twtab<W, L>(tab, M));
+        else
+            block_dft<W, L, S, POS_FAST, false>(vv, lds, s, j, p.P, lshift, p.nmask, M);
     };
     forward(v);
 #pragma unroll
@@ -228,10 +302,7 @@ __device__ __forceinline__ void small_conv_tile(const typename W::word* f, const
 // (<= 168 VGPRs) without spilling: measured 13% faster at 1024 than the
 // unconstrained allocation (two waves).  Longer tiles, 64-bit words and the
 // quotient (more registers) would spill there.
-// Tiles whose inter-pass twiddles sit in an LDS table (PassTab<L>) beside the
-// exchange buffer: (w, w/m) pairs while both fit half a CU's LDS, else w alone
-// (w/m formed at use).
-constexpr bool small_tab(int L) { return L >= 32 && L <= (1 << SMALL_MAX_LOG2N); }
+
 template <int L, int S>
 constexpr bool small_tab_pairs() {
     return 8 * Blk<L, S, POS_FAST>::LDS_DOUBLES + 16 * PassTab<L>::SIZE <= 80 * 1024;
@@ -249,7 +320,13 @@ __global__ __launch_bounds__(256, (small_waves_per_eu(L, OP, W::WB))) void k_con
     const uint32_t cnt = (uint32_t)(count - first < (uint64_t)S ? count - first : (uint64_t)S);
     // (the one-wave tiles keep the global table: a table per 64 threads would
     // cost more LDS, and more loads to fill, than it saves)
-    if constexpr (small_tab(L) && S == small_s(L)) {
+    if constexpr (small_tab(L) && S == small_s(L) && small_split(L)) {
+        __shared__ double2 tab[SplitTab<L>::SIZE];
+        fill_split_tab<L>(tab, p, p.logn);
+        __syncthreads();
+        small_conv_tile<W, L, S, OP, true, double2>(f, g, h, offs ? offs + first : nullptr, first * L, cnt, p, lds,
+                                                    threadIdx.x, singular, tab);
+    } else if constexpr (small_tab(L) && S == small_s(L)) {
         using TE = typename std::conditional<small_tab_pairs<L, S>(), double2, double>::type;
         __shared__ TE tab[PassTab<L>::SIZE];
         fill_pass_tab<L>(tab, p, p.logn);
@@ -284,8 +361,15 @@ __global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, ty
         for (int i = 0; i < B::E; ++i) v[i] = W::mul_var(v[i], W::load_reduce(y[off + B::pos0(j, i)], M), M);
     }
     // (one transform per tile: the table pays where it keeps three or more
-    // workgroups per CU; at 2048 and 4096 it measured even and 6-13% slower)
-    if constexpr (small_tab(L) && L <= 1024) {
+    // workgroups per CU; at 2048 and 4096 the full table measured even and
+    // 6-13% slower than the global power table, the split one 17-26% faster)
+    if constexpr (small_split(L)) {
+        __shared__ double2 tab[SplitTab<L>::SIZE];
+        fill_split_tab<L, double2, INV>(tab, p, p.logn);
+        __syncthreads();
+        block_dft_tw<W, L, S, POS_FAST, INV>(v, lds, s, j, p.P, p.logn - B::l, p.nmask, M,
+                                             TwSplit<W, L, double2>{tab, M});
+    } else if constexpr (small_tab(L) && L <= 1024) {
         using TE = typename std::conditional<small_tab_pairs<L, S>(), double2, double>::type;
         __shared__ TE tab[PassTab<L>::SIZE];
         fill_pass_tab<L, TE, INV>(tab, p, p.logn);
