@@ -12,11 +12,12 @@
 // pass takes radix R0 = 2^(log2 L mod 4) (when that is not 0) so that every
 // later pass is radix 16.  Passes exchange data through LDS.
 //
-// Range: every pass input is reduced (|x| <= m/2 + 2): pass 0 by the caller,
-// later passes by the inter-pass twiddle product, which is applied even when
-// the twiddle is 1.  Inside DFT_R only the non-trivial twiddles multiply, so a
-// pass output is at most R (m/2 + 2) <= 8m + 32 in magnitude, well inside the
-// 48m limit of the product.
+// Range: later passes take reduced inputs (|x| <= m/2 + 2), from the
+// inter-pass twiddle product, which is applied even when the twiddle is 1;
+// pass 0 takes the caller's, reduced or (32-bit words) canonical, |x| < m.
+// Inside DFT_R only the non-trivial twiddles multiply, so a pass output is at
+// most R (m/2 + 2) <= 8m + 32 in magnitude, the first pass's at most 16 m:
+// inside the 48m limit of the product.
 #pragma once
 #include "arith.hpp"
 

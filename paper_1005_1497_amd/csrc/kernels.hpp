@@ -27,6 +27,35 @@ namespace nttmi {
 #define NTT_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 #define NTT_LARGE_CASES(X) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22)
 
+// Pass-0 inputs of a transform of two or more passes from E operand words.
+// Such a transform takes pass-0 inputs of magnitude up to m as well as reduced
+// ones: the first pass's outputs are then at most 16 m, inside the 48 m limit
+// of the inter-pass twiddle product that reduces them.  So 32-bit words that
+// are all below m in the wave (canonical operands, the usual case) enter as
+// they are, and the E reductions are replaced by one maximum; a wave with any
+// word at or above m reduces them all.  64-bit words are always reduced: their
+// product limit is 12 m.  (Used by the four-step column phase; in the LDS
+// tiles the extra live values cost a wave of occupancy.)
+template <class W, int E>
+__device__ __forceinline__ void load_pass0(double* v, const typename W::word* w, const ModC& M) {
+    if constexpr (W::WB == 4) {
+        // each word is converted as it arrives (no word stays live)
+        uint32_t mx = 0;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            v[i] = (double)w[i];
+            mx = w[i] > mx ? w[i] : mx;
+        }
+        if (__builtin_amdgcn_ballot_w64((double)mx >= M.m) != 0) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = reduce(v[i], M);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = W::load_reduce(w[i], M);
+    }
+}
+
 // ------------------------------------------------------------------ small N
 // Convolutions per workgroup of the LDS kernels: 256 threads (small_s), or one
 // wave per tile up to L = 1024 (small_s_wave), which spreads a short batch over
@@ -613,8 +642,7 @@ __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typena
     typename Tw4<W>::T tw4[B::E];
 #pragma unroll
     for (int i = 0; i < B::E; ++i) tw4[i] = Tw4<W>::ld(bt, j * G::A + t1, B::posL(0, i) * G::A);
-#pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = W::load_reduce(in.w[i], M);
+    load_pass0<W, B::E>(v, in.w, M);
     block_dft_tw<W, G::Bn, G::SC, SEQ_FAST, false>(v, L.xch, s, j, p.P, G::la, G::N - 1, M,
                                                    twtab<W, G::Bn>(L.colf, M));
 #pragma unroll

@@ -9,7 +9,8 @@
 //   32-bit words (m < 2^24)
 //     mulmod(b, w, w/m)   |b| m < 2^53 - m, 0 <= w < m  ->  r = b w mod m, |r| <= m/2 + 2
 //                         (|b| up to 48 m for m = 13631489, 32 m near 2^24;
-//                         the kernels' products have |b| <= 8 m + 32)
+//                         the kernels' products have |b| <= 16 m: a first-pass
+//                         output of canonical words; later passes' <= 8 m + 32)
 //     mulmod_var(a, b)    |a b| < 2^53 - m          ->  r = a b mod m, |r| <= m/2 + 2
 //     reduce(y)           |y| < 2^51                ->  r = y mod m,   |r| <= m/2 + 2
 //     canon_u32(y)        as reduce                 ->  the canonical residue
@@ -88,7 +89,7 @@ static void sweep32(int64_t m, long cases) {
     const ModC M = make_modc((uint64_t)m);
     const double rb = (double)m / 2 + 2;
     const int64_t bfit = (int64_t)((((int64_t)1 << 53) - 2 * m) / m);   // |b| m < 2^53 - m
-    const int64_t bmax = 48 * m - 1 < bfit ? 48 * m - 1 : bfit, fmax = 8 * m + 32;
+    const int64_t bmax = 48 * m - 1 < bfit ? 48 * m - 1 : bfit, fmax = 16 * m;
     for (long i = 0; i < cases; ++i) {
         // twiddle product, uniform and adversarial
         int64_t b = uni(-bmax, bmax);
@@ -98,7 +99,8 @@ static void sweep32(int64_t m, long cases) {
         if (i % 64 == 3) w = m - 1;
         const double2 tw = tw_pair((uint64_t)w, (uint64_t)m);
         check("mulmod", m, mulmod((double)b, tw.x, tw.y, M), (i128)b * w, rb, (double)b, (double)w);
-        // variable product: a pass output times a reduced value, or a twiddle
+        // variable product: a pass output (up to a first pass's 16 m) times a
+        // reduced value, or a twiddle
         int64_t a = uni(-fmax, fmax);
         int64_t c = (i & 1) ? uni(-(m / 2 + 2), m / 2 + 2) : uni(0, m - 1);
         if (i % 4 == 3 && modp(a, m) != 0) c = adversarial_w(a, m, (int)i) - ((i & 1) ? m : 0);
