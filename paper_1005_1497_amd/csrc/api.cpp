@@ -515,7 +515,7 @@ ntt_status conv_one(const Plan* p, uint32_t wbits, uint32_t log2n, const void* f
     ntt_status st = get_buf(caches().work, stream, ((size_t)2 * (wbits / 8)) << log2n, &ws);
     if (st != NTT_OK) return st;
     count(NTT_COUNT_FOURSTEP);
-    return hip_status(launch_conv_fourstep((int)wbits, log2n, f, g, h, 1, 0, ws, p->dev, s));
+    return hip_status(launch_conv_fourstep((int)wbits, log2n, f, g, h, 1, 0, ws, p->dev, s, nullptr, (uint32_t)cu_count()));
 }
 
 // `batch` contiguous rows of N = 2^log2n, forward or inverse, plan built.  The
@@ -535,7 +535,7 @@ ntt_status ntt_rows(const Plan* p, uint32_t elem_bits, uint32_t log2n, bool inv,
     for (uint32_t r = 0; r < batch; r += chunk) {
         const uint32_t k = std::min(chunk, batch - r);
         const hipError_t e = launch_ntt_fourstep((int)elem_bits, log2n, inv, (const char*)x + (size_t)r * per,
-                                                 (char*)X + (size_t)r * per, k, ws, p->dev, s);
+                                                 (char*)X + (size_t)r * per, k, ws, p->dev, s, (uint32_t)cu_count());
         if (e != hipSuccess) return hip_status(e);
     }
     return NTT_OK;
@@ -584,7 +584,7 @@ ntt_status launch_items(uint32_t n, uint32_t c, uint64_t base, const uint64_t* d
         if (e != NTT_OK) return e;
         count(NTT_COUNT_FOURSTEP);
         return hip_status(launch_conv_fourstep((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, c,
-                                               1ull << n, ws, p->dev, s));
+                                               1ull << n, ws, p->dev, s, nullptr, (uint32_t)cu_count()));
     };
     if (form == CF_FOURSTEP && fourstep_ok) return fourstep();
     // persistent fused form: grid = resident workgroups, bounded by a 1 GiB
@@ -944,7 +944,8 @@ ntt_status conv_circular_noalloc(uint64_t m, uint32_t log2n, uint64_t root, uint
     const hipError_t e = noalloc_scratch(&ws);
     if (e != hipSuccess) return hip_status(e);
     count(NTT_COUNT_FOURSTEP);
-    return hip_status(launch_conv_fourstep((int)elem_bits, log2n, f, g, h, 1, 0, ws, p->dev, s));
+    return hip_status(launch_conv_fourstep((int)elem_bits, log2n, f, g, h, 1, 0, ws, p->dev, s, nullptr,
+                                           (uint32_t)cu_count()));
 }
 
 ntt_status conv_deconvolve(uint64_t m, uint32_t log2n, uint64_t root, uint32_t elem_bits, const void* f,

@@ -420,13 +420,15 @@ __global__ __launch_bounds__(256) void k_ntt_small(const typename W::word* x, ty
 // Geometry for N = 2^LOGN = A * B, A = 2^fs_la(LOGN) (row length),
 // B = N / A (column length).  Element t = t1 + A t2 (t1 < A, t2 < B),
 // frequency u = u2 + B u1.  Scratch rows: Y[u2 * A + t1].
-template <int LOGN>
+template <int LOGN, int TT = 512>
 struct FS {
     static constexpr int la = fs_la(LOGN), lb = LOGN - fs_la(LOGN);
     static constexpr int A = 1 << la, Bn = 1 << lb, N = 1 << LOGN;
     // threads per workgroup: 512, so that a column block of B = 256 spans 32
-    // columns (128-byte rows of a block: whole cache lines)
-    static constexpr int T = 512;
+    // columns (128-byte rows of a block: whole cache lines); 256 for the
+    // multi-launch kernels of batches too short to fill the chip with
+    // 512-thread blocks (16 columns, half lines, twice the workgroups)
+    static constexpr int T = TT;
     static constexpr int SC = 16 * T / Bn; // columns per block
     static constexpr int SR = 16 * T / A;  // rows per block
     using BC = Blk<Bn, SC, SEQ_FAST>;
@@ -546,9 +548,9 @@ __device__ __forceinline__ void st_scr(const Buf& b, double y, uint32_t ve, uint
 // workgroups per CU and no kernel fills a table it does not read.
 constexpr int LDS_HALF_CU = 80 * 1024;
 enum { FS_ALL = 0, FS_COL = 1, FS_ROW = 2 };
-template <int LOGN, int PART = FS_ALL>
+template <int LOGN, int PART = FS_ALL, int TT = 512>
 struct FSLds {
-    using G = FS<LOGN>;
+    using G = FS<LOGN, TT>;
     static constexpr bool SAME = (G::A == G::Bn);
     static constexpr int TC = PassTab<G::Bn>::SIZE;   // entries per column table
     static constexpr int TR = PassTab<G::A>::SIZE;    // entries per row table
@@ -570,9 +572,9 @@ struct FSLds {
 
 
 // Where the exchange buffer and the twiddle tables sit in `lds`.
-template <int LOGN, int PART = FS_ALL>
-__device__ __forceinline__ FSLds<LOGN, PART> fs_lds_layout(double* lds) {
-    using FL = FSLds<LOGN, PART>;
+template <int LOGN, int PART = FS_ALL, int TT = 512>
+__device__ __forceinline__ FSLds<LOGN, PART, TT> fs_lds_layout(double* lds) {
+    using FL = FSLds<LOGN, PART, TT>;
     FL L;
     L.xch = lds;
     typename FL::Entry* t = reinterpret_cast<typename FL::Entry*>(lds + FL::XCH2);
@@ -582,19 +584,19 @@ __device__ __forceinline__ FSLds<LOGN, PART> fs_lds_layout(double* lds) {
 }
 
 // Fills the twiddle tables of plan p; ends with a barrier.
-template <int LOGN, int PART>
-__device__ __forceinline__ void fs_lds_fill(const FSLds<LOGN, PART>& L, const DevPlan& p) {
-    using G = FS<LOGN>;
-    using FL = FSLds<LOGN, PART>;
+template <int LOGN, int PART, int TT>
+__device__ __forceinline__ void fs_lds_fill(const FSLds<LOGN, PART, TT>& L, const DevPlan& p) {
+    using G = FS<LOGN, TT>;
+    using FL = FSLds<LOGN, PART, TT>;
     using E = typename FL::Entry;
     if constexpr (FL::HASC) fill_pass_tab<G::Bn>(const_cast<E*>(L.colf), p, LOGN);
     if constexpr (FL::HASR) fill_pass_tab<G::A>(const_cast<E*>(L.rowf), p, LOGN);
     __syncthreads();
 }
 
-template <int LOGN, int PART = FS_ALL>
-__device__ __forceinline__ FSLds<LOGN, PART> fs_lds_init(double* lds, const DevPlan& p) {
-    const FSLds<LOGN, PART> L = fs_lds_layout<LOGN, PART>(lds);
+template <int LOGN, int PART = FS_ALL, int TT = 512>
+__device__ __forceinline__ FSLds<LOGN, PART, TT> fs_lds_init(double* lds, const DevPlan& p) {
+    const FSLds<LOGN, PART, TT> L = fs_lds_layout<LOGN, PART, TT>(lds);
     fs_lds_fill<LOGN>(L, p);
     return L;
 }
@@ -604,22 +606,22 @@ __device__ __forceinline__ FSLds<LOGN, PART> fs_lds_init(double* lds, const DevP
 // (natural order, any 32-bit values), times w^(t1 u2), into scratch rows.
 // Positions of a work item are j + const(i), so every access is a buffer
 // access with one per-lane offset and a compile-time uniform offset.
-template <class W, int LOGN>
+template <class W, int LOGN, int TT = 512>
 struct ColIn {
-    typename W::word w[FS<LOGN>::BC::E];
+    typename W::word w[FS<LOGN, TT>::BC::E];
 };
 
 // Raw loads of a forward column block (issued ahead of its transform).
 // Positions of a work item are j + const(i), so every access is a buffer
 // access with one per-lane offset and a compile-time uniform offset.
-template <class W, int LOGN>
-__device__ __forceinline__ ColIn<W, LOGN> col_fwd_load(const typename W::word* x, int c0) {
-    using G = FS<LOGN>;
+template <class W, int LOGN, int TT = 512>
+__device__ __forceinline__ ColIn<W, LOGN, TT> col_fwd_load(const typename W::word* x, int c0) {
+    using G = FS<LOGN, TT>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const Buf bx(x, G::N * W::WB);
-    ColIn<W, LOGN> in;
+    ColIn<W, LOGN, TT> in;
 #pragma unroll
     for (int i = 0; i < B::E; ++i) in.w[i] = ld_word_s<W>(bx, c0 + s + G::A * j, G::A * B::pos0(0, i));
     return in;
@@ -627,10 +629,10 @@ __device__ __forceinline__ ColIn<W, LOGN> col_fwd_load(const typename W::word* x
 
 // Column phase, forward: length-B transforms of columns c0..c0+SC of x
 // (natural order), times w^(t1 u2), into scratch rows Y[u2 * A + t1].
-template <class W, int LOGN, int PART>
-__device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typename W::sword* Y, int c0,
-                                                const DevPlan& p, const FSLds<LOGN, PART>& L) {
-    using G = FS<LOGN>;
+template <class W, int LOGN, int PART, int TT>
+__device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN, TT>& in, typename W::sword* Y, int c0,
+                                                const DevPlan& p, const FSLds<LOGN, PART, TT>& L) {
+    using G = FS<LOGN, TT>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
@@ -650,10 +652,10 @@ __device__ __forceinline__ void col_fwd_compute(const ColIn<W, LOGN>& in, typena
         st_scr<W>(by, W::mul_w(v[i], (double)tw4[i], M), j * G::A + t1, B::posL(0, i) * G::A);
 }
 
-template <class W, int LOGN, int PART>
+template <class W, int LOGN, int PART, int TT>
 __device__ __forceinline__ void col_fwd_block(const typename W::word* x, typename W::sword* Y, int c0,
-                                              const DevPlan& p, const FSLds<LOGN, PART>& L) {
-    col_fwd_compute<W, LOGN>(col_fwd_load<W, LOGN>(x, c0), Y, c0, p, L);
+                                              const DevPlan& p, const FSLds<LOGN, PART, TT>& L) {
+    col_fwd_compute<W, LOGN>(col_fwd_load<W, LOGN, TT>(x, c0), Y, c0, p, L);
 }
 
 // Where the row phases of the inverse store: row position s1 of row u2 goes to
@@ -674,22 +676,22 @@ __device__ __forceinline__ uint32_t scr_row_shift(int u2, int j) {
 // row), product with N^-1, then the first half of the inverse four-step as a
 // forward one (row transforms, times w^(t1 u2)), back into Yf; the inverse
 // column phase negates the output index.
-template <class W, int LOGN>
+template <class W, int LOGN, int TT = 512>
 struct RowIn {
-    typename W::sword f[FS<LOGN>::BR::E];
-    typename W::sword g[FS<LOGN>::BR::E];
+    typename W::sword f[FS<LOGN, TT>::BR::E];
+    typename W::sword g[FS<LOGN, TT>::BR::E];
 };
 
-template <class W, int LOGN>
-__device__ __forceinline__ RowIn<W, LOGN> row_conv_load(const typename W::sword* Yf, const typename W::sword* Yg,
+template <class W, int LOGN, int TT = 512>
+__device__ __forceinline__ RowIn<W, LOGN, TT> row_conv_load(const typename W::sword* Yf, const typename W::sword* Yg,
                                                         int r0) {
-    using G = FS<LOGN>;
+    using G = FS<LOGN, TT>;
     using B = typename G::BR;
     int s, j;
     B::item(threadIdx.x, s, j);
     const Buf bf(Yf, G::N * W::SB), bg(Yg, G::N * W::SB);
     const uint32_t rowoff = (uint32_t)((r0 + s) * G::A + j);
-    RowIn<W, LOGN> in;
+    RowIn<W, LOGN, TT> in;
 #pragma unroll
     for (int i = 0; i < B::E; ++i) in.f[i] = ld_scr_raw<W>(bf, rowoff, B::pos0(0, i));
 #pragma unroll
@@ -701,11 +703,11 @@ __device__ __forceinline__ RowIn<W, LOGN> row_conv_load(const typename W::sword*
 // independent work around each exchange, about 2% faster at 2^17..2^19, but
 // about 32 more VGPRs); the kernels limited to 128 VGPRs take them one after
 // the other.
-template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL>
-__device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typename W::sword* Yf, int r0,
-                                                 const DevPlan& p, const FSLds<LOGN, PART>& L,
+template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL, int TT = 512>
+__device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN, TT>& in, typename W::sword* Yf, int r0,
+                                                 const DevPlan& p, const FSLds<LOGN, PART, TT>& L,
                                                  uint32_t* singular = nullptr) {
-    using G = FS<LOGN>;
+    using G = FS<LOGN, TT>;
     using B = typename G::BR;
     int s, j;
     B::item(threadIdx.x, s, j);
@@ -760,11 +762,11 @@ __device__ __forceinline__ void row_conv_compute(const RowIn<W, LOGN>& in, typen
     for (int i = 1; i < B::E; ++i) st_scr<W>(bf, W::mul_w(v[i], (double)tw4[i], M), rowoff, B::posL(0, i) - 1);
 }
 
-template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL>
+template <class W, int LOGN, int OP = OP_MUL, bool LOCKSTEP = true, int PART = FS_ALL, int TT = 512>
 __device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const typename W::sword* Yg, int r0,
-                                               const DevPlan& p, const FSLds<LOGN, PART>& L,
+                                               const DevPlan& p, const FSLds<LOGN, PART, TT>& L,
                                                uint32_t* singular = nullptr) {
-    row_conv_compute<W, LOGN, OP, LOCKSTEP>(row_conv_load<W, LOGN>(Yf, Yg, r0), Yf, r0, p, L, singular);
+    row_conv_compute<W, LOGN, OP, LOCKSTEP>(row_conv_load<W, LOGN, TT>(Yf, Yg, r0), Yf, r0, p, L, singular);
 }
 
 // Column phase, inverse: length-B transforms of scratch columns, optional
@@ -775,26 +777,26 @@ __device__ __forceinline__ void row_conv_block(typename W::sword* Yf, const type
 // position (t1 - 1) mod A (scr_row_shift), so those columns sit at positions
 // A - 1 - (c0 + s): the SC positions ending at A - 1 - c0, one whole block of
 // cache lines, read in ascending order.
-template <class W, int LOGN>
+template <class W, int LOGN, int TT = 512>
 struct ColInvIn {
-    typename W::sword w[FS<LOGN>::BC::E];
+    typename W::sword w[FS<LOGN, TT>::BC::E];
 };
 
-template <int LOGN>
+template <int LOGN, int TT = 512>
 __device__ __forceinline__ uint32_t col_inv_src(int c0, int s) {
-    using G = FS<LOGN>;
+    using G = FS<LOGN, TT>;
     return (uint32_t)(G::A - c0 - G::SC + s);
 }
 
-template <class W, int LOGN>
-__device__ __forceinline__ ColInvIn<W, LOGN> col_inv_load(const typename W::sword* Y, int c0) {
-    using G = FS<LOGN>;
+template <class W, int LOGN, int TT = 512>
+__device__ __forceinline__ ColInvIn<W, LOGN, TT> col_inv_load(const typename W::sword* Y, int c0) {
+    using G = FS<LOGN, TT>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
     const Buf by(Y, G::N * W::SB);
-    const uint32_t off = (uint32_t)(j * G::A) + col_inv_src<LOGN>(c0, s);
-    ColInvIn<W, LOGN> in;
+    const uint32_t off = (uint32_t)(j * G::A) + col_inv_src<LOGN, TT>(c0, s);
+    ColInvIn<W, LOGN, TT> in;
 #pragma unroll
     for (int i = 0; i < B::E; ++i) in.w[i] = ld_scr_raw<W>(by, off, B::pos0(0, i) * G::A);
     return in;
@@ -828,11 +830,11 @@ struct NegStore {
     __device__ static constexpr uint32_t reg(int i) { return FS<LOGN>::A * FS<LOGN>::BC::posL(0, 15 - i); }
 };
 
-template <class W, int LOGN, bool SCALE, bool CRT = false, int PART = FS_ALL>
-__device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typename W::word* x, int c0,
-                                                const DevPlan& p, const FSLds<LOGN, PART>& L,
+template <class W, int LOGN, bool SCALE, bool CRT = false, int PART = FS_ALL, int TT = 512>
+__device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN, TT>& in, typename W::word* x, int c0,
+                                                const DevPlan& p, const FSLds<LOGN, PART, TT>& L,
                                                 const CrtStore& crt = CrtStore{}) {
-    using G = FS<LOGN>;
+    using G = FS<LOGN, TT>;
     using B = typename G::BC;
     int s, j;
     B::item(threadIdx.x, s, j);
@@ -885,17 +887,17 @@ __device__ __forceinline__ void col_inv_compute(const ColInvIn<W, LOGN>& in, typ
     }
 }
 
-template <class W, int LOGN, bool SCALE, int PART>
+template <class W, int LOGN, bool SCALE, int PART, int TT>
 __device__ __forceinline__ void col_inv_block(const typename W::sword* Y, typename W::word* x, int c0,
-                                              const DevPlan& p, const FSLds<LOGN, PART>& L) {
-    col_inv_compute<W, LOGN, SCALE>(col_inv_load<W, LOGN>(Y, c0), x, c0, p, L);
+                                              const DevPlan& p, const FSLds<LOGN, PART, TT>& L) {
+    col_inv_compute<W, LOGN, SCALE>(col_inv_load<W, LOGN, TT>(Y, c0), x, c0, p, L);
 }
 
 // Row phase of the natural-order forward transform: X[u2 + B u1].
-template <class W, int LOGN, int PART>
+template <class W, int LOGN, int PART, int TT>
 __device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, typename W::word* X, int r0,
-                                                  const DevPlan& p, const FSLds<LOGN, PART>& L) {
-    using G = FS<LOGN>;
+                                                  const DevPlan& p, const FSLds<LOGN, PART, TT>& L) {
+    using G = FS<LOGN, TT>;
     using B = typename G::BRS;
     int s, j;
     B::item(threadIdx.x, s, j);
@@ -914,10 +916,10 @@ __device__ __forceinline__ void row_fwd_nat_block(const typename W::sword* Y, ty
 // Row phase of the natural-order inverse transform: from X[u2 + B u1] to
 // scratch rows: forward row transforms times w^(u2 s1) (the inverse column
 // phase negates the output index).
-template <class W, int LOGN, int PART>
+template <class W, int LOGN, int PART, int TT>
 __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typename W::sword* Y, int r0,
-                                                  const DevPlan& p, const FSLds<LOGN, PART>& L) {
-    using G = FS<LOGN>;
+                                                  const DevPlan& p, const FSLds<LOGN, PART, TT>& L) {
+    using G = FS<LOGN, TT>;
     using B = typename G::BRS;
     int s, j;
     B::item(threadIdx.x, s, j);
@@ -949,62 +951,62 @@ __device__ __forceinline__ void row_inv_nat_block(const typename W::word* X, typ
 // faster; transform rows of 2048 10-17% faster, of 512 and 1024 2-14% slower;
 // a grid-strided loop at rows of 256 7% slower.
 constexpr int FS_ROW_LOOP_CONV = 9, FS_ROW_LOOP_NAT = 11;
-template <class W, int LOGN>
-__global__ __launch_bounds__(512) void k_fs_col_fwd(const typename W::word* x, typename W::sword* Y,
+template <class W, int LOGN, int TT>
+__global__ __launch_bounds__(TT) void k_fs_col_fwd(const typename W::word* x, typename W::sword* Y,
                                                     uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN, FS_COL>::WORDS];
-    const FSLds<LOGN, FS_COL> L = fs_lds_init<LOGN, FS_COL>(lds, p);
-    col_fwd_block<W, LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN>::SC, p, L);
+    __shared__ double lds[FSLds<LOGN, FS_COL, TT>::WORDS];
+    const FSLds<LOGN, FS_COL, TT> L = fs_lds_init<LOGN, FS_COL, TT>(lds, p);
+    col_fwd_block<W, LOGN>(x + blockIdx.y * item_stride, Y + blockIdx.y * ystride, blockIdx.x * FS<LOGN, TT>::SC, p, L);
 }
 // Column phase of both operands in one launch: grid.y = 2 * items, the first
 // half f (into Y_f), the second g (into Y_g = Y_f + N).
-template <class W, int LOGN>
-__global__ __launch_bounds__(512) void k_fs_col_fwd2(const typename W::word* f, const typename W::word* g,
+template <class W, int LOGN, int TT>
+__global__ __launch_bounds__(TT) void k_fs_col_fwd2(const typename W::word* f, const typename W::word* g,
                                                      typename W::sword* Y, uint64_t item_stride, uint64_t ystride,
                                                      uint32_t items, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN, FS_COL>::WORDS];
-    const FSLds<LOGN, FS_COL> L = fs_lds_init<LOGN, FS_COL>(lds, p);
+    __shared__ double lds[FSLds<LOGN, FS_COL, TT>::WORDS];
+    const FSLds<LOGN, FS_COL, TT> L = fs_lds_init<LOGN, FS_COL, TT>(lds, p);
     const uint32_t second = blockIdx.y >= items ? 1u : 0u;
     const uint32_t item = blockIdx.y - second * items;
-    col_fwd_block<W, LOGN>((second ? g : f) + item * item_stride, Y + item * ystride + second * FS<LOGN>::N,
-                           blockIdx.x * FS<LOGN>::SC, p, L);
+    col_fwd_block<W, LOGN>((second ? g : f) + item * item_stride, Y + item * ystride + second * FS<LOGN, TT>::N,
+                           blockIdx.x * FS<LOGN, TT>::SC, p, L);
 }
-template <class W, int LOGN, int OP>
-__global__ __launch_bounds__(512) void k_fs_row_conv(typename W::sword* Yf, const typename W::sword* Yg,
+template <class W, int LOGN, int OP, int TT>
+__global__ __launch_bounds__(TT) void k_fs_row_conv(typename W::sword* Yf, const typename W::sword* Yg,
                                                      uint64_t ystride, DevPlan p, uint32_t* singular) {
-    __shared__ double lds[FSLds<LOGN, FS_ROW>::WORDS];
-    const FSLds<LOGN, FS_ROW> L = fs_lds_init<LOGN, FS_ROW>(lds, p);
-    const uint32_t bstep = FS<LOGN>::la >= FS_ROW_LOOP_CONV ? gridDim.x : FS<LOGN>::Bn / FS<LOGN>::SR;
-    for (uint32_t b = blockIdx.x; b < (uint32_t)(FS<LOGN>::Bn / FS<LOGN>::SR); b += bstep)
-        row_conv_block<W, LOGN, OP>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, (int)b * FS<LOGN>::SR, p,
+    __shared__ double lds[FSLds<LOGN, FS_ROW, TT>::WORDS];
+    const FSLds<LOGN, FS_ROW, TT> L = fs_lds_init<LOGN, FS_ROW, TT>(lds, p);
+    const uint32_t bstep = FS<LOGN, TT>::la >= FS_ROW_LOOP_CONV ? gridDim.x : FS<LOGN, TT>::Bn / FS<LOGN, TT>::SR;
+    for (uint32_t b = blockIdx.x; b < (uint32_t)(FS<LOGN, TT>::Bn / FS<LOGN, TT>::SR); b += bstep)
+        row_conv_block<W, LOGN, OP>(Yf + blockIdx.y * ystride, Yg + blockIdx.y * ystride, (int)b * FS<LOGN, TT>::SR, p,
                                     L, singular);
 }
-template <class W, int LOGN, bool SCALE>
-__global__ __launch_bounds__(512) void k_fs_col_inv(const typename W::sword* Y, typename W::word* x,
+template <class W, int LOGN, bool SCALE, int TT>
+__global__ __launch_bounds__(TT) void k_fs_col_inv(const typename W::sword* Y, typename W::word* x,
                                                     uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN, FS_COL>::WORDS];
-    const FSLds<LOGN, FS_COL> L = fs_lds_init<LOGN, FS_COL>(lds, p);
-    col_inv_block<W, LOGN, SCALE>(Y + blockIdx.y * ystride, x + blockIdx.y * item_stride, blockIdx.x * FS<LOGN>::SC,
+    __shared__ double lds[FSLds<LOGN, FS_COL, TT>::WORDS];
+    const FSLds<LOGN, FS_COL, TT> L = fs_lds_init<LOGN, FS_COL, TT>(lds, p);
+    col_inv_block<W, LOGN, SCALE>(Y + blockIdx.y * ystride, x + blockIdx.y * item_stride, blockIdx.x * FS<LOGN, TT>::SC,
                                   p, L);
 }
-template <class W, int LOGN>
-__global__ __launch_bounds__(512) void k_fs_row_fwd_nat(const typename W::sword* Y, typename W::word* X,
+template <class W, int LOGN, int TT>
+__global__ __launch_bounds__(TT) void k_fs_row_fwd_nat(const typename W::sword* Y, typename W::word* X,
                                                         uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN, FS_ROW>::WORDS];
-    const FSLds<LOGN, FS_ROW> L = fs_lds_init<LOGN, FS_ROW>(lds, p);
-    const uint32_t bstep = FS<LOGN>::la >= FS_ROW_LOOP_NAT ? gridDim.x : FS<LOGN>::Bn / FS<LOGN>::SR;
-    for (uint32_t b = blockIdx.x; b < (uint32_t)(FS<LOGN>::Bn / FS<LOGN>::SR); b += bstep)
-        row_fwd_nat_block<W, LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, (int)b * FS<LOGN>::SR, p,
+    __shared__ double lds[FSLds<LOGN, FS_ROW, TT>::WORDS];
+    const FSLds<LOGN, FS_ROW, TT> L = fs_lds_init<LOGN, FS_ROW, TT>(lds, p);
+    const uint32_t bstep = FS<LOGN, TT>::la >= FS_ROW_LOOP_NAT ? gridDim.x : FS<LOGN, TT>::Bn / FS<LOGN, TT>::SR;
+    for (uint32_t b = blockIdx.x; b < (uint32_t)(FS<LOGN, TT>::Bn / FS<LOGN, TT>::SR); b += bstep)
+        row_fwd_nat_block<W, LOGN>(Y + blockIdx.y * ystride, X + blockIdx.y * item_stride, (int)b * FS<LOGN, TT>::SR, p,
                                    L);
 }
-template <class W, int LOGN>
-__global__ __launch_bounds__(512) void k_fs_row_inv_nat(const typename W::word* X, typename W::sword* Y,
+template <class W, int LOGN, int TT>
+__global__ __launch_bounds__(TT) void k_fs_row_inv_nat(const typename W::word* X, typename W::sword* Y,
                                                         uint64_t item_stride, uint64_t ystride, DevPlan p) {
-    __shared__ double lds[FSLds<LOGN, FS_ROW>::WORDS];
-    const FSLds<LOGN, FS_ROW> L = fs_lds_init<LOGN, FS_ROW>(lds, p);
-    const uint32_t bstep = FS<LOGN>::la >= FS_ROW_LOOP_NAT ? gridDim.x : FS<LOGN>::Bn / FS<LOGN>::SR;
-    for (uint32_t b = blockIdx.x; b < (uint32_t)(FS<LOGN>::Bn / FS<LOGN>::SR); b += bstep)
-        row_inv_nat_block<W, LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, (int)b * FS<LOGN>::SR, p,
+    __shared__ double lds[FSLds<LOGN, FS_ROW, TT>::WORDS];
+    const FSLds<LOGN, FS_ROW, TT> L = fs_lds_init<LOGN, FS_ROW, TT>(lds, p);
+    const uint32_t bstep = FS<LOGN, TT>::la >= FS_ROW_LOOP_NAT ? gridDim.x : FS<LOGN, TT>::Bn / FS<LOGN, TT>::SR;
+    for (uint32_t b = blockIdx.x; b < (uint32_t)(FS<LOGN, TT>::Bn / FS<LOGN, TT>::SR); b += bstep)
+        row_inv_nat_block<W, LOGN>(X + blockIdx.y * item_stride, Y + blockIdx.y * ystride, (int)b * FS<LOGN, TT>::SR, p,
                                    L);
 }
 

@@ -50,12 +50,14 @@ hipError_t launch_conv_small(int wbits, int logn, const void* f, const void* g, 
                              uint32_t* singular = nullptr);
 hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, const DevPlan& p,
                             hipStream_t st, const void* y = nullptr);
-// scratch: items * 2N scratch words (conv), batch * N (ntt); scratch words are wbits/8 bytes
+// scratch: items * 2N scratch words (conv), batch * N (ntt); scratch words are
+// wbits/8 bytes.  cus: the device's compute units (the workgroup size is
+// halved when 512-thread column blocks would not give each of them one).
 hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
                                 uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
-                                uint32_t* singular = nullptr);
+                                uint32_t* singular, uint32_t cus);
 hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
-                               const DevPlan& p, hipStream_t st);
+                               const DevPlan& p, hipStream_t st, uint32_t cus);
 // scratch: grid * 2N scratch words; queue: two uint32 work-queue words, zero
 // before the launch and zero again after it (launches sharing a queue must be
 // ordered, e.g. on one stream).  singular != null selects the deconvolution

@@ -1,9 +1,11 @@
 """GPU parity of the multi-launch four-step kernels in the launch shapes where
 their row kernels take several row blocks per workgroup (rows of 512 and more
 positions in a convolution, 2048 in a natural-order transform, with enough
-items that the launch narrows its grid), checked against the one-item launches
-and the oracle (Eq. 1 sampled per item; Eq. 2 on sampled bins of every row;
-Eq. 3 through the round trip)."""
+items that the launch narrows its grid), and of the two workgroup sizes (a
+batch whose 512-thread column blocks fill the chip keeps them; one item runs
+256-thread blocks), each checked against the one-item launches and the oracle
+(Eq. 1 sampled per item; Eq. 2 on sampled bins of every row; Eq. 3 through the
+round trip)."""
 import numpy as np
 import pytest
 import torch
@@ -66,3 +68,32 @@ def test_ntt_rows_with_row_loops(nt):
     assert np.array_equal(got, ref.astype(np.uint32))
     y = host(nt.ntt_inverse(X, M))
     assert np.array_equal(y, x)
+
+
+@pytest.mark.parametrize("n,count", [(13, 200), (14, 100), (15, 100), (16, 100)])
+def test_fourstep_workgroup_sizes_agree(nt, n, count):
+    # count is large enough that the batch's 512-thread column blocks give
+    # every CU one, and below two thirds of the fused kernel's residency, so
+    # the batch runs the 512-thread four-step kernels; each item alone
+    # (FLAG_PER_ITEM) runs the 256-thread ones
+    N = 1 << n
+    rng = np.random.default_rng(200 + n)
+    f = rng.integers(0, M, count * N, dtype=np.uint32)
+    g = rng.integers(0, M, count * N, dtype=np.uint32)
+    f[:N] = M - 1                      # item 0 at the top of the canonical range
+    desc = nt.BatchDesc([n] * count, [i * N for i in range(count)])
+    before = nt.launch_counts()
+    h = host(nt.conv_batched(dev(f), dev(g), desc, M))
+    assert _delta(nt, before)["fourstep"] == 1
+    h1 = host(nt.conv_batched(dev(f), dev(g), desc, M, flags=nt.FLAG_PER_ITEM))
+    assert np.array_equal(h, h1)
+    for i in (0, count - 1):
+        idx = np.unique(np.concatenate([[0, 1, N // 2, N - 1], rng.integers(0, N, 12)])).astype(np.uint64)
+        ref = oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], M, idx)
+        assert np.array_equal(h[i * N + idx.astype(np.int64)], ref.astype(np.uint32)), i
+    # transforms: 64 rows (512-thread blocks from 2^15 on) against one row
+    x = rng.integers(0, M, (64, N), dtype=np.uint32)
+    X = host(nt.ntt_forward(dev(x), M))
+    X0 = host(nt.ntt_forward(dev(x[:1]), M))
+    assert np.array_equal(X[:1], X0)
+    assert np.array_equal(host(nt.ntt_inverse(dev(X0), M)), x[:1])
