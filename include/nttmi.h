@@ -69,7 +69,8 @@ typedef enum {
                                         batch (one persistent launch or one launch per
                                         length; per length: LDS tile of 256 threads or
                                         of one wave, fused kernel at full or one-per-CU
-                                        occupancy, or the unfused four-step launches),
+                                        occupancy, or the unfused four-step launches
+                                        with 512- or 256-thread workgroups),
                                         keep the fastest for every later batch of the
                                         same shape (lengths, item counts rounded down to
                                         powers of two, m, word width, device), and run

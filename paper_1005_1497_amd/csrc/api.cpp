@@ -44,7 +44,9 @@ enum ClassForm : uint8_t {
     CF_DEFAULT = 0,      // LDS kernel of 256 threads / persistent fused kernel at full occupancy
     CF_SMALL_WAVE = 1,   // LDS kernel with one wave per workgroup
     CF_FUSED_ONE = 2,    // persistent fused kernel, one workgroup per CU
-    CF_FOURSTEP = 3,     // unfused four-step: column, row and column launches over all items
+    CF_FOURSTEP = 3,     // unfused four-step: column, row and column launches over all items,
+                         // 512-thread blocks
+    CF_FOURSTEP_256 = 4, // the same with 256-thread blocks (twice the workgroups per phase)
 };
 struct BatchForm {
     bool multi = false;
@@ -578,15 +580,17 @@ ntt_status launch_items(uint32_t n, uint32_t c, uint64_t base, const uint64_t* d
     // multi-launch four-step form: every phase spreads all items over the
     // chip; scratch 2N words per item, within 1 GiB
     const bool fourstep_ok = contiguous && (((uint64_t)2 * c * wb) << n) <= (1ull << 30);
+    // (workgroup size: by the default rule, or as the form names it)
     auto fourstep = [&]() -> ntt_status {
         void* ws = nullptr;
         const ntt_status e = get_buf(caches().work, stream, (size_t)(((uint64_t)2 * c * wb) << n), &ws);
         if (e != NTT_OK) return e;
         count(NTT_COUNT_FOURSTEP);
+        const int tt = form == CF_FOURSTEP ? 512 : (form == CF_FOURSTEP_256 ? 256 : 0);
         return hip_status(launch_conv_fourstep((int)elem_bits, n, F + base * wb, G + base * wb, H + base * wb, c,
-                                               1ull << n, ws, p->dev, s, nullptr, (uint32_t)cu_count()));
+                                               1ull << n, ws, p->dev, s, nullptr, (uint32_t)cu_count(), tt));
     };
-    if (form == CF_FOURSTEP && fourstep_ok) return fourstep();
+    if ((form == CF_FOURSTEP || form == CF_FOURSTEP_256) && fourstep_ok) return fourstep();
     // persistent fused form: grid = resident workgroups, bounded by a 1 GiB
     // scratch budget (2N words per workgroup)
     // tuning override: NTTMI_FUSED_WG_PER_CU caps resident workgroups per CU
@@ -810,6 +814,7 @@ ntt_status autotune(const std::map<uint32_t, std::vector<uint64_t>>& cls, std::m
         } else {
             if (fused_blocks_per_cu((int)elem_bits, n) > 1) cand.push_back(CF_FUSED_ONE);
             cand.push_back(CF_FOURSTEP);
+            if (n <= FOURSTEP_256_MAX_LOG2N) cand.push_back(CF_FOURSTEP_256);
         }
         float tbest = 3.4e38f;
         uint8_t fbest = CF_DEFAULT;

@@ -52,10 +52,13 @@ hipError_t launch_ntt_small(int wbits, int logn, bool inv, const void* x, void* 
                             hipStream_t st, const void* y = nullptr);
 // scratch: items * 2N scratch words (conv), batch * N (ntt); scratch words are
 // wbits/8 bytes.  cus: the device's compute units (the workgroup size is
-// halved when 512-thread column blocks would not give each of them one).
+// halved when 512-thread column blocks would not give each of them one).  tt:
+// 0 for that rule, or 256 / 512 threads per workgroup (256 only up to
+// 2^FOURSTEP_256_MAX_LOG2N; above it 512).
+constexpr int FOURSTEP_256_MAX_LOG2N = 19;
 hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
                                 uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
-                                uint32_t* singular, uint32_t cus);
+                                uint32_t* singular, uint32_t cus, int tt = 0);
 hipError_t launch_ntt_fourstep(int wbits, int logn, bool inv, const void* x, void* X, uint32_t batch, void* scratch,
                                const DevPlan& p, hipStream_t st, uint32_t cus);
 // scratch: grid * 2N scratch words; queue: two uint32 work-queue words, zero

@@ -26,7 +26,7 @@ static uint32_t fs_row_grid(int la, int loop_la, uint32_t rblocks, uint32_t item
 // 512).  Lengths up to 2^19, whose columns have 64 positions or more, so that
 // a 256-thread block still stores 16 whole columns (64-byte row segments).
 static bool fs_narrow(int logn, uint64_t blocks512, uint32_t cus) {
-    return logn <= 19 && blocks512 < (uint64_t)cus;
+    return logn <= FOURSTEP_256_MAX_LOG2N && blocks512 < (uint64_t)cus;
 }
 
 template <class W, int n, int TT>
@@ -61,10 +61,11 @@ static hipError_t conv_fourstep_g(const void* f, const void* g, void* h, uint32_
 
 template <class W, int n>
 static hipError_t conv_fourstep_n(const void* f, const void* g, void* h, uint32_t items, uint64_t item_stride,
-                                  void* scratch, const DevPlan& p, hipStream_t st, uint32_t* singular, uint32_t cus) {
+                                  void* scratch, const DevPlan& p, hipStream_t st, uint32_t* singular, uint32_t cus,
+                                  int tt) {
     using G = FS<n>;
-    if constexpr (n <= 19) {
-        if (fs_narrow(n, 2ull * items * (G::A / G::SC), cus))
+    if constexpr (n <= FOURSTEP_256_MAX_LOG2N) {
+        if (tt == 256 || (tt == 0 && fs_narrow(n, 2ull * items * (G::A / G::SC), cus)))
             return conv_fourstep_g<W, n, 256>(f, g, h, items, item_stride, scratch, p, st, singular);
     }
     return conv_fourstep_g<W, n, 512>(f, g, h, items, item_stride, scratch, p, st, singular);
@@ -73,10 +74,10 @@ static hipError_t conv_fourstep_n(const void* f, const void* g, void* h, uint32_
 template <class W>
 static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* h, uint32_t items,
                                   uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
-                                  uint32_t* singular, uint32_t cus) {
+                                  uint32_t* singular, uint32_t cus, int tt) {
     switch (logn) {
 #define CASE(n) \
-    case n: return conv_fourstep_n<W, n>(f, g, h, items, item_stride, scratch, p, st, singular, cus);
+    case n: return conv_fourstep_n<W, n>(f, g, h, items, item_stride, scratch, p, st, singular, cus, tt);
         NTT_LARGE_CASES(CASE)
 #undef CASE
         default:
@@ -86,10 +87,10 @@ static hipError_t conv_fourstep_t(int logn, const void* f, const void* g, void* 
 
 hipError_t launch_conv_fourstep(int wbits, int logn, const void* f, const void* g, void* h, uint32_t items,
                                 uint64_t item_stride, void* scratch, const DevPlan& p, hipStream_t st,
-                                uint32_t* singular, uint32_t cus) {
+                                uint32_t* singular, uint32_t cus, int tt) {
     if (items == 0) return hipSuccess;
-    return wbits == 32 ? conv_fourstep_t<W32>(logn, f, g, h, items, item_stride, scratch, p, st, singular, cus)
-                       : conv_fourstep_t<W64>(logn, f, g, h, items, item_stride, scratch, p, st, singular, cus);
+    return wbits == 32 ? conv_fourstep_t<W32>(logn, f, g, h, items, item_stride, scratch, p, st, singular, cus, tt)
+                       : conv_fourstep_t<W64>(logn, f, g, h, items, item_stride, scratch, p, st, singular, cus, tt);
 }
 
 template <class W, int n, int TT>
@@ -116,7 +117,7 @@ template <class W, int n>
 static hipError_t ntt_fourstep_n(bool inv, const void* x, void* X, uint32_t batch, void* scratch, const DevPlan& p,
                                  hipStream_t st, uint32_t cus) {
     using G = FS<n>;
-    if constexpr (n <= 19) {
+    if constexpr (n <= FOURSTEP_256_MAX_LOG2N) {
         if (fs_narrow(n, (uint64_t)batch * (G::A / G::SC), cus))
             return ntt_fourstep_g<W, n, 256>(inv, x, X, batch, scratch, p, st);
     }
