@@ -427,7 +427,8 @@ struct FS {
     // threads per workgroup: 512, so that a column block of B = 256 spans 32
     // columns (128-byte rows of a block: whole cache lines); 256 for the
     // multi-launch kernels of batches too short to fill the chip with
-    // 512-thread blocks (16 columns, half lines, twice the workgroups)
+    // 512-thread blocks (half the columns and rows per block, twice the
+    // workgroups)
     static constexpr int T = TT;
     static constexpr int SC = 16 * T / Bn; // columns per block
     static constexpr int SR = 16 * T / A;  // rows per block

@@ -23,8 +23,9 @@ static uint32_t fs_row_grid(int la, int loop_la, uint32_t rblocks, uint32_t item
 // one, halving the blocks doubles their number (measured for one item: 2^16
 // 18.5 -> 15.6 us, 2^18 23.0 -> 19.8 us, 2^19 28.3 -> 22.9 us; for 8 items of
 // 2^18, 1024 blocks of 256 threads, 38.1 -> 42.4 us, so larger batches keep
-// 512).  Lengths up to 2^19, whose columns have 64 positions or more, so that
-// a 256-thread block still stores 16 whole columns (64-byte row segments).
+// 512).  Lengths up to 2^19 only: their columns have at most 256 positions,
+// so that a 256-thread block still spans 16 columns or more (row segments of
+// 64 bytes or more).
 static bool fs_narrow(int logn, uint64_t blocks512, uint32_t cus) {
     return logn <= FOURSTEP_256_MAX_LOG2N && blocks512 < (uint64_t)cus;
 }
