@@ -206,6 +206,10 @@ def main():
     ap.add_argument("--rhos", default="0.3,0.5,0.7,0.9", help="serve-sweep: the offered loads")
     ap.add_argument("--streams", type=int, default=4, help="serve-sweep: streams of the native scheduler")
     ap.add_argument("--inflight", type=int, default=4, help="serve-sweep: batches in flight (native scheduler)")
+    ap.add_argument("--arenas", choices=("host", "device"), default="host",
+                    help="serve, serve-sweep: the native scheduler's arenas: pinned host memory that the kernels read "
+                         "and write directly (ntt_server_create_host), or device memory with copies each way "
+                         "(ntt_server_create)")
     ap.add_argument("--solo", type=int, default=16,
                     help="serve-sweep: requests of 2^SOLO words and more run as batches of their own (0: never)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -701,13 +705,14 @@ def serve_bench(args):
                 "peak_inflight_batches": st.peak_inflight, "elapsed_s": el}
 
     def run_native(rate, max_batch=512):
-        """The library's scheduler thread (ntt_server_*): a producer thread
-        submits with Poisson gaps (the copy into pinned staging runs inside the
-        library), a consumer thread collects the results in order into a reused
+        """The library's scheduler thread (ntt_server_*; --arenas): a producer
+        thread submits with Poisson gaps (the copy into the request's pinned
+        slot or staging block runs inside the library), a consumer thread collects the results in order into a reused
         buffer; latency is measured inside the library from submission to
         completion."""
         srv = sv.NativeConvServer(m, capacity_log2=cap, elem_bits=64, streams=4, max_batch=max_batch,
-                                  max_batch_elems=1 << (cap - 2), max_inflight=4)
+                                  max_batch_elems=1 << (cap - 2), max_inflight=4,
+                                  host_arenas=args.arenas == "host")
         for t in [srv.submit(f, g) for f, g in reqs[:warm]]:
             srv.result(t)
         srv.stats(reset=True)
@@ -776,7 +781,9 @@ def serve_bench(args):
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
         "latency_ms": {"p50": nat["p50_ms"], "p99": nat["p99_ms"]},
         "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "rho": args.rho,
-                   "offered_per_s": nat_rate, "scheduler": "native (ntt_server_*)", "words": "u64", "streams": 4,
+                   "offered_per_s": nat_rate,
+                   "scheduler": "native (ntt_server_*), %s arenas" % args.arenas,
+                   "words": "u64", "streams": 4,
                    "max_batch_elems": 1 << (cap - 2)},
         "saturated": nat_sat, "served": nat,
         "forms": {"native_at_python_rate": nat_same, "native_one_request_per_batch_at_python_rate": nat_single,
@@ -792,7 +799,8 @@ def serve_sweep(args):
     """The served workload at several offered loads: --requests timed requests
     (20000 by default here) after 1000 warm-up ones, lengths 2^n with n uniform
     in [8, 18], m = 31065037602817 (64-bit words), Poisson arrivals at rho times
-    the saturated throughput of the library's native scheduler; beside each,
+    the saturated throughput of the library's native scheduler (--arenas: host
+    arenas by default); beside each,
     the same arrivals served one launch sequence per request (Python
     scheduler, one request per batch) where that form keeps up, and that form
     at rho times its own saturated throughput.  Every request has operands of
@@ -823,7 +831,7 @@ def serve_sweep(args):
     def native(rate, max_batch=512):
         srv = sv.NativeConvServer(m, capacity_log2=cap, elem_bits=64, streams=args.streams, max_batch=max_batch,
                                   max_batch_elems=1 << (cap - 2), max_inflight=args.inflight,
-                                  solo_log2n=args.solo)
+                                  solo_log2n=args.solo, host_arenas=args.arenas == "host")
         for t in [srv.submit(f, g) for f, g in reqs[:warm]]:
             srv.result(t)
         srv.stats(reset=True)
@@ -911,7 +919,8 @@ def serve_sweep(args):
     print(json.dumps({"metric": "served exact convolutions: p50/p99 latency across offered loads",
                       "unit": "ms", "n_gpus": 1, "requests": n, "warmup": warm, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "words": "u64",
-                                 "scheduler": "native (ntt_server_*)", "streams": args.streams,
+                                 "scheduler": "native (ntt_server_*), %s arenas" % args.arenas,
+                                 "streams": args.streams,
                                  "max_inflight": args.inflight, "solo_log2n": args.solo,
                                  "max_batch_elems": 1 << (cap - 2)},
                       "saturated": sat, "one_launch_per_request_saturated": single_sat, "sweep": rows}), flush=True)

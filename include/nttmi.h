@@ -255,8 +255,10 @@ ntt_status ntt_euler_root(uint64_t m, uint32_t log2n, uint64_t *root);
 ntt_status ntt_copy_batch(void *const *dst, const void *const *src, const uint64_t *bytes, uint32_t count,
                           void *stream);
 
-/* Native served form (plumbing around conv_batched, no arithmetic of its own):
- * a server owns three device arenas of 2^arena_log2 words (f, g, h), a set of
+/* Native served form (plumbing around conv_batched, no arithmetic of its own).
+ * ntt_server_create: a server owns three device arenas of 2^arena_log2 words
+ * (f, g, h; ntt_server_create_host keeps them in pinned host memory instead,
+ * see there), a set of
  * non-blocking streams and one scheduler thread.  ntt_server_submit copies a
  * request's operands (host memory) into a pinned staging block and queues it;
  * the scheduler admits queued requests in arrival order while a buddy
@@ -280,10 +282,24 @@ ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order,
                              uint32_t arena_log2, uint32_t streams, uint32_t max_batch, uint64_t max_batch_elems,
                              uint32_t max_inflight, ntt_server **out);
 
+/* A server whose arenas are pinned host memory that the batch kernels read
+ * and write directly over the host link: a request takes its slot when it is
+ * submitted or staged (the same offset in three host arenas, chunks of
+ * 2^arena_log2 words, a new chunk when the others are full), submit copies f
+ * and g into it, a batch is requests of one chunk run by one conv_batched call
+ * with no copies before or after it, and ntt_server_wait copies the result
+ * out of the slot and frees it.  The device holds only the batch kernels'
+ * scratch.  For requests whose transfer time matters more than the kernels'
+ * (the kernels then load operands at the host link's rate).  Arguments and
+ * errors as for ntt_server_create; every other ntt_server_* call applies. */
+ntt_status ntt_server_create_host(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
+                                  uint32_t arena_log2, uint32_t streams, uint32_t max_batch,
+                                  uint64_t max_batch_elems, uint32_t max_inflight, ntt_server **out);
+
 /* Queues the convolution of f and g (host arrays of 2^log2n words each, read
  * before the call returns) and writes its ticket.  NTT_E_LENGTH: log2n above
  * root_log2order or arena_log2; NTT_E_ARG: null pointer or a stopped server;
- * NTT_E_NOMEM: no pinned staging memory. */
+ * NTT_E_NOMEM: no pinned staging memory (or host arena chunk). */
 ntt_status ntt_server_submit(ntt_server *srv, const void *f, const void *g, uint32_t log2n, uint64_t *ticket);
 
 /* Zero-copy submission, first half: reserves a staging block for a request of

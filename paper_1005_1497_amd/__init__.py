@@ -100,6 +100,8 @@ def _load():
     D = ctypes.c_double
     L.ntt_server_create.argtypes = [U64, U64, U32, U32, U32, U32, U32, U64, U32, ctypes.POINTER(VP)]
     L.ntt_server_create.restype = I32
+    L.ntt_server_create_host.argtypes = [U64, U64, U32, U32, U32, U32, U32, U64, U32, ctypes.POINTER(VP)]
+    L.ntt_server_create_host.restype = I32
     L.ntt_server_submit.argtypes = [VP, VP, VP, U32, ctypes.POINTER(U64)]
     L.ntt_server_submit.restype = I32
     L.ntt_server_stage.argtypes = [VP, U32, ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(U64)]

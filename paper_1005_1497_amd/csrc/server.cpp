@@ -1,13 +1,21 @@
 // Native served form: continuous batching of circular convolutions behind the
 // C ABI (ntt_server_*).  Host code only: the arithmetic runs in conv_batched.
 //
-// A request's life: submit copies f and g into a pinned staging block (rows f,
-// g, h) and queues the request; the scheduler thread admits queued requests in
-// arrival order into slots of a buddy allocator over three device arenas,
-// uploads each batch's rows, runs one conv_batched over the batch on the next
-// stream, downloads the results into the staging blocks and records an event;
-// when the event has passed, the slots are freed and waiters are woken; wait
-// copies the result out and returns the staging block to the pool.
+// A request's life (device arenas): submit copies f and g into a pinned staging
+// block (rows f, g, h) and queues the request; the scheduler thread admits
+// queued requests in arrival order into slots of a buddy allocator over three
+// device arenas, uploads each batch's rows, runs one conv_batched over the
+// batch on the next stream, downloads the results into the staging blocks and
+// records an event; when the event has passed, the slots are freed and waiters
+// are woken; wait copies the result out and returns the staging block to the
+// pool.
+//
+// Host arenas (ntt_server_create_host): the slot is taken at submission, in
+// three pinned host arenas (chunks of 2^arena_log2 words, a new chunk when the
+// others are full) that the device reads and writes directly; submit copies f
+// and g into the slot, a batch is requests of one chunk and one conv_batched
+// call whose kernels load f, g and store h there (no copies), and wait copies
+// the result out and frees the slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,11 +109,20 @@ class PinnedPool {
 
 enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2, Q_FAILED = 3, Q_STAGED = 4 };
 
+// Host arenas: three pinned arenas of 2^top words, read and written by the
+// batch kernels at the addresses the device sees (dF, dG, dH).
+struct Chunk {
+    char *F = nullptr, *G = nullptr, *H = nullptr;
+    void *dF = nullptr, *dG = nullptr, *dH = nullptr;
+    Buddy buddy{0};
+};
+
 struct Req {
     uint64_t id = 0;
     uint32_t log2n = 0;
     uint64_t off = 0;
-    char* staging = nullptr;   // f, g, h rows of 2^log2n words
+    Chunk* chunk = nullptr;    // host arenas: the chunk holding the slot
+    char* staging = nullptr;   // device arenas: f, g, h rows of 2^log2n words
     size_t staging_bytes = 0;
     Clock::time_point arrival;
     int state = Q_QUEUED;
@@ -131,6 +148,8 @@ struct ntt_server {
     uint32_t solo_log2n = 16;
     size_t wb = 4;
     int dev = 0;
+    bool host = false;                 // host arenas (ntt_server_create_host)
+    std::vector<Chunk*> chunks;        // host arenas, guarded by mu
     char *F = nullptr, *G = nullptr, *H = nullptr;
     std::vector<hipStream_t> streams;
     size_t next_stream = 0;
@@ -164,7 +183,32 @@ struct ntt_server {
 
     void run();
     bool launch(std::vector<Req*>& adm);
+    Chunk* host_slot(uint32_t log2n, uint64_t* off);
 };
+
+// Host arenas: a slot of 2^log2n words in the first chunk with room, else in a
+// new chunk; null when pinned memory runs out.  Called with mu held.
+Chunk* ntt_server::host_slot(uint32_t log2n, uint64_t* off) {
+    for (Chunk* c : chunks)
+        if (c->buddy.alloc((int)log2n, off)) return c;
+    const size_t bytes = (size_t(1) << arena_log2) * wb;
+    Chunk* c = new Chunk();
+    c->buddy = Buddy((int)arena_log2);
+    hipError_t e = hipHostMalloc((void**)&c->F, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->G, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->H, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&c->dF, c->F, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&c->dG, c->G, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&c->dH, c->H, 0);
+    if (e != hipSuccess || !c->buddy.alloc((int)log2n, off)) {
+        for (char* p : {c->F, c->G, c->H})
+            if (p) (void)hipHostFree(p);
+        delete c;
+        return nullptr;
+    }
+    chunks.push_back(c);
+    return c;
+}
 
 // Uploads, convolves and downloads one admitted batch; false if a HIP call or
 // conv_batched failed (nothing of the batch is then in flight).
@@ -173,7 +217,11 @@ bool ntt_server::launch(std::vector<Req*>& adm) {
     std::vector<uint8_t> lg(adm.size());
     std::vector<uint64_t> off(adm.size());
     hipError_t e = hipSuccess;
-    for (size_t i = 0; i < adm.size() && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < adm.size() && host; ++i) {
+        lg[i] = (uint8_t)adm[i]->log2n;
+        off[i] = adm[i]->off;
+    }
+    for (size_t i = 0; i < adm.size() && e == hipSuccess && !host; ++i) {
         Req* r = adm[i];
         const size_t row = (size_t(1) << r->log2n) * wb;
         lg[i] = (uint8_t)r->log2n;
@@ -182,13 +230,17 @@ bool ntt_server::launch(std::vector<Req*>& adm) {
         if (e == hipSuccess) e = hipMemcpyAsync(G + r->off * wb, r->staging + row, row, hipMemcpyHostToDevice, s);
     }
     ntt_batch_desc d{(uint32_t)adm.size(), lg.data(), off.data()};
-    if (e != hipSuccess || conv_batched(m, root, rlo, bits, &d, F, G, H, NTT_FLAG_TRANSIENT, s) != NTT_OK) {
+    // host arenas: one chunk per batch (admission keeps it so)
+    const void* bF = host ? adm[0]->chunk->dF : (const void*)F;
+    const void* bG = host ? adm[0]->chunk->dG : (const void*)G;
+    void* bH = host ? adm[0]->chunk->dH : (void*)H;
+    if (e != hipSuccess || conv_batched(m, root, rlo, bits, &d, bF, bG, bH, NTT_FLAG_TRANSIENT, s) != NTT_OK) {
         // copies already enqueued may still run: let them finish before the
         // caller frees the slots
         (void)hipStreamSynchronize(s);
         return false;
     }
-    for (size_t i = 0; i < adm.size() && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < adm.size() && e == hipSuccess && !host; ++i) {
         Req* r = adm[i];
         const size_t row = (size_t(1) << r->log2n) * wb;
         e = hipMemcpyAsync(r->staging + 2 * row, H + r->off * wb, row, hipMemcpyDeviceToHost, s);
@@ -231,10 +283,14 @@ void ntt_server::run() {
                 const uint64_t size = 1ull << r->log2n;
                 const bool solo = solo_log2n != 0 && r->log2n >= solo_log2n;
                 if (!adm.empty() && (solo || elems + size > max_batch_elems)) break;
-                uint64_t o = 0;
-                if (!buddy.alloc((int)r->log2n, &o)) break;
+                if (host) {
+                    if (!adm.empty() && r->chunk != adm[0]->chunk) break;
+                } else {
+                    uint64_t o = 0;
+                    if (!buddy.alloc((int)r->log2n, &o)) break;
+                    r->off = o;
+                }
                 queue.pop_front();
-                r->off = o;
                 r->state = Q_RUNNING;
                 elems += size;
                 adm.push_back(r);
@@ -248,7 +304,7 @@ void ntt_server::run() {
             lk.lock();
             if (!ok) {
                 for (Req* r : adm) {
-                    buddy.release(r->off, (int)r->log2n);
+                    if (!host) buddy.release(r->off, (int)r->log2n);
                     r->state = Q_FAILED;
                 }
                 cv_done.notify_all();
@@ -264,7 +320,7 @@ void ntt_server::run() {
             }
             const auto now = Clock::now();
             for (Req* r : inflight[i].reqs) {
-                buddy.release(r->off, (int)r->log2n);
+                if (!host) buddy.release(r->off, (int)r->log2n);   // host arenas: freed by wait
                 r->state = q == hipSuccess ? Q_DONE : Q_FAILED;
                 if (q == hipSuccess) record_latency(std::chrono::duration<double, std::milli>(now - r->arrival).count());
             }
@@ -283,11 +339,12 @@ void ntt_server::run() {
     }
 }
 
-extern "C" {
+namespace {
 
-ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
-                             uint32_t arena_log2, uint32_t streams, uint32_t max_batch, uint64_t max_batch_elems,
-                             uint32_t max_inflight, ntt_server** out) {
+// ntt_server_create / ntt_server_create_host: device or host arenas.
+ntt_status create_server(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits, uint32_t arena_log2,
+                         uint32_t streams, uint32_t max_batch, uint64_t max_batch_elems, uint32_t max_inflight,
+                         bool host, ntt_server** out) {
     if (!out) return NTT_E_ARG;
     *out = nullptr;
     if (arena_log2 > 28 || streams < 1 || streams > 16 || max_batch < 1 || max_inflight < 1) return NTT_E_ARG;
@@ -309,11 +366,12 @@ ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order,
     s->max_inflight = max_inflight;
     s->max_batch_elems = max_batch_elems ? max_batch_elems : (1ull << arena_log2);
     s->buddy = Buddy((int)arena_log2);
+    s->host = host;
     hipError_t e = hipGetDevice(&s->dev);
     const size_t bytes = (size_t(1) << arena_log2) * s->wb;
-    if (e == hipSuccess) e = hipMalloc((void**)&s->F, bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&s->G, bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&s->H, bytes);
+    if (e == hipSuccess && !host) e = hipMalloc((void**)&s->F, bytes);
+    if (e == hipSuccess && !host) e = hipMalloc((void**)&s->G, bytes);
+    if (e == hipSuccess && !host) e = hipMalloc((void**)&s->H, bytes);
     // the largest scratch a batch launch takes: at most two resident
     // workgroups per CU, 2N words each for N up to the arena, and never more
     // than 1 GiB; reserved with each stream's work queue now rather than on
@@ -343,11 +401,61 @@ ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order,
     return NTT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+ntt_status ntt_server_create(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
+                             uint32_t arena_log2, uint32_t streams, uint32_t max_batch, uint64_t max_batch_elems,
+                             uint32_t max_inflight, ntt_server** out) {
+    return create_server(m, root, root_log2order, elem_bits, arena_log2, streams, max_batch, max_batch_elems,
+                         max_inflight, false, out);
+}
+
+ntt_status ntt_server_create_host(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
+                                  uint32_t arena_log2, uint32_t streams, uint32_t max_batch,
+                                  uint64_t max_batch_elems, uint32_t max_inflight, ntt_server** out) {
+    return create_server(m, root, root_log2order, elem_bits, arena_log2, streams, max_batch, max_batch_elems,
+                         max_inflight, true, out);
+}
+
 ntt_status ntt_server_submit(ntt_server* s, const void* f, const void* g, uint32_t log2n, uint64_t* ticket) {
     if (!s || !f || !g || !ticket) return NTT_E_ARG;
     if (log2n > s->rlo || log2n > s->arena_log2) return NTT_E_LENGTH;
     const auto arrival = Clock::now();
     const size_t row = (size_t(1) << log2n) * s->wb;
+    if (s->host) {
+        // the slot first (under the lock), the copies outside it, then queued
+        Req* r = new Req();
+        r->log2n = log2n;
+        r->state = Q_STAGED;
+        char *fp = nullptr, *gp = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            Chunk* c = s->stop ? nullptr : s->host_slot(log2n, &r->off);
+            if (!c) {
+                const bool stopped = s->stop;
+                delete r;
+                return stopped ? NTT_E_ARG : NTT_E_NOMEM;
+            }
+            r->chunk = c;
+            r->id = s->next_id++;
+            s->reqs[r->id] = r;
+            fp = c->F + r->off * s->wb;
+            gp = c->G + r->off * s->wb;
+        }
+        std::memcpy(fp, f, row);
+        std::memcpy(gp, g, row);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            r->arrival = arrival;
+            r->state = Q_QUEUED;
+            s->queue.push_back(r);
+            *ticket = r->id;
+        }
+        s->cv_sched.notify_one();
+        return NTT_OK;
+    }
     char* st = (char*)s->pool.get(3 * row);
     if (!st) return NTT_E_NOMEM;
     std::memcpy(st, f, row);
@@ -377,6 +485,25 @@ ntt_status ntt_server_stage(ntt_server* s, uint32_t log2n, void** f, void** g, u
     if (!s || !f || !g || !ticket) return NTT_E_ARG;
     if (log2n > s->rlo || log2n > s->arena_log2) return NTT_E_LENGTH;
     const size_t row = (size_t(1) << log2n) * s->wb;
+    if (s->host) {
+        Req* r = new Req();
+        r->log2n = log2n;
+        r->state = Q_STAGED;
+        std::lock_guard<std::mutex> lk(s->mu);
+        Chunk* c = s->stop ? nullptr : s->host_slot(log2n, &r->off);
+        if (!c) {
+            const bool stopped = s->stop;
+            delete r;
+            return stopped ? NTT_E_ARG : NTT_E_NOMEM;
+        }
+        r->chunk = c;
+        r->id = s->next_id++;
+        s->reqs[r->id] = r;
+        *ticket = r->id;
+        *f = c->F + r->off * s->wb;
+        *g = c->G + r->off * s->wb;
+        return NTT_OK;
+    }
     char* st = (char*)s->pool.get(3 * row);
     if (!st) return NTT_E_NOMEM;
     Req* r = new Req();
@@ -434,8 +561,15 @@ ntt_status ntt_server_wait(ntt_server* s, uint64_t ticket, void* h, double timeo
     lk.unlock();
     const size_t row = (size_t(1) << r->log2n) * s->wb;
     const bool ok = r->state == Q_DONE;
-    if (ok) std::memcpy(h, r->staging + 2 * row, row);
-    s->pool.put(r->staging, r->staging_bytes);
+    if (s->host) {
+        if (ok) std::memcpy(h, r->chunk->H + r->off * s->wb, row);
+        lk.lock();
+        r->chunk->buddy.release(r->off, (int)r->log2n);
+        lk.unlock();
+    } else {
+        if (ok) std::memcpy(h, r->staging + 2 * row, row);
+        s->pool.put(r->staging, r->staging_bytes);
+    }
     delete r;
     return ok ? NTT_OK : NTT_E_DEVICE;
 }
@@ -483,17 +617,21 @@ void ntt_server_destroy(ntt_server* s) {
     s->cv_sched.notify_all();
     if (s->th.joinable()) s->th.join();   // the thread drains the queue and the batches in flight first
     for (auto& kv : s->reqs) {
-        s->pool.put(kv.second->staging, kv.second->staging_bytes);
+        if (!s->host) s->pool.put(kv.second->staging, kv.second->staging_bytes);
         delete kv.second;
+    }
+    for (Chunk* c : s->chunks) {
+        for (char* p : {c->F, c->G, c->H}) (void)hipHostFree(p);
+        delete c;
     }
     for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
     for (hipStream_t h : s->streams) {
         nttmi::release_stream_caches(h);
         (void)hipStreamDestroy(h);
     }
-    (void)hipFree(s->F);
-    (void)hipFree(s->G);
-    (void)hipFree(s->H);
+    if (s->F) (void)hipFree(s->F);
+    if (s->G) (void)hipFree(s->G);
+    if (s->H) (void)hipFree(s->H);
     delete s;
 }
 

@@ -411,19 +411,23 @@ class NativeConvServer:
     in the C ABI): the same admission, batching and stream rotation as
     ConvServer, with no Python on the per-request path.  submit() copies f and
     g into a pinned staging block inside the library (the interpreter lock is
-    released during the call) and returns a ticket; result() waits for it."""
+    released during the call) and returns a ticket; result() waits for it.
+    host_arenas=True creates the server with ntt_server_create_host: the
+    request's slot is in pinned host arenas that the batch kernels read and
+    write directly, with no copies between host and device."""
 
     def __init__(self, m: int, capacity_log2: int, elem_bits: int = 64, streams: int = 4, max_batch: int = 512,
                  max_batch_elems: int = 0, max_inflight: int = 4, root: int = 2, root_log2order: int | None = None,
-                 solo_log2n: int | None = None):
+                 solo_log2n: int | None = None, host_arenas: bool = False):
         import ctypes
         import paper_1005_1497_amd as nt
         self._nt, self._ct = nt, ctypes
         self.np_dtype = np.uint64 if elem_bits == 64 else np.uint32
         rlo = root_log2order if root_log2order is not None else nt.modulus_order(m)
         h = ctypes.c_void_p()
-        nt._check(nt.lib.ntt_server_create(m, root, rlo, elem_bits, capacity_log2, streams, max_batch,
-                                            max_batch_elems, max_inflight, ctypes.byref(h)), "ntt_server_create")
+        create = nt.lib.ntt_server_create_host if host_arenas else nt.lib.ntt_server_create
+        nt._check(create(m, root, rlo, elem_bits, capacity_log2, streams, max_batch, max_batch_elems, max_inflight,
+                         ctypes.byref(h)), "ntt_server_create")
         self._h = h
         if solo_log2n is not None:   # else the library's default (2^16 words and more run alone)
             nt._check(nt.lib.ntt_server_set_solo(h, int(solo_log2n)), "ntt_server_set_solo")

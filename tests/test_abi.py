@@ -49,6 +49,8 @@ def lib():
     L.ntt_copy_batch.restype = I32
     L.ntt_server_create.argtypes = [U64, U64, U32, U32, U32, U32, U32, U64, U32, ctypes.POINTER(VP)]
     L.ntt_server_create.restype = I32
+    L.ntt_server_create_host.argtypes = [U64, U64, U32, U32, U32, U32, U32, U64, U32, ctypes.POINTER(VP)]
+    L.ntt_server_create_host.restype = I32
     L.ntt_server_submit.argtypes = [VP, VP, VP, U32, ctypes.POINTER(U64)]
     L.ntt_server_submit.restype = I32
     L.ntt_server_stage.argtypes = [VP, U32, VP, VP, VP]
@@ -226,6 +228,9 @@ def test_server_argument_validation(lib):
     assert lib.ntt_server_create(M, 2, 19, 32, 20, 17, 512, 0, 4, ctypes.byref(h)) == 1  # too many streams
     assert lib.ntt_server_create(M, 2, 19, 32, 20, 4, 0, 0, 4, ctypes.byref(h)) == 1    # empty batches
     assert lib.ntt_server_create(M, 2, 19, 32, 20, 4, 512, 0, 0, ctypes.byref(h)) == 1  # nothing in flight
+    assert lib.ntt_server_create_host(M, 2, 19, 32, 20, 4, 512, 0, 4, None) == 1       # no out pointer
+    assert lib.ntt_server_create_host(M, 2, 19, 32, 29, 4, 512, 0, 4, ctypes.byref(h)) == 1  # arena too large
+    assert lib.ntt_server_create_host(M, 2, 19, 32, 20, 0, 512, 0, 4, ctypes.byref(h)) == 1  # no stream
     assert lib.ntt_server_create(M + 2, 2, 19, 32, 20, 4, 512, 0, 4, ctypes.byref(h)) == 2  # not a valid modulus
     assert lib.ntt_server_create(M, 3, 19, 32, 20, 4, 512, 0, 4, ctypes.byref(h)) == 4  # 3 has not order 2^19
     t = ctypes.c_uint64()

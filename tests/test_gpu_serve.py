@@ -74,11 +74,14 @@ def test_zero_copy_submission_and_result_lifetime():
         assert np.array_equal(fu.result(), host(nt.conv_circular(dev(f), dev(g), m)))
 
 
+@pytest.mark.parametrize("host_arenas", [False, True])
 @pytest.mark.parametrize("solo", [None, 0])
 @pytest.mark.parametrize("bits,m", [(64, si.M_U64), (32, si.M_13631489)])
-def test_native_server_equals_alone(bits, m, solo):
+def test_native_server_equals_alone(bits, m, solo, host_arenas):
     # solo None: the default admission (requests of 2^16 words and more run as
-    # batches of their own); 0: every length may share a batch
+    # batches of their own); 0: every length may share a batch.  host_arenas:
+    # the slots are in pinned host arenas that the kernels read and write
+    # directly (several chunks here: 200 staged requests exceed one)
     # the library's own scheduler thread: every result equals the request run
     # alone; two client threads submit at once; the oracle checks a few
     # entries.  Operands are staged first and the threads only queue them, so
@@ -93,7 +96,7 @@ def test_native_server_equals_alone(bits, m, solo):
     dt = np.uint64 if bits == 64 else np.uint32
     reqs = [(rng.integers(0, m, 1 << int(n), dtype=dt), rng.integers(0, m, 1 << int(n), dtype=dt)) for n in lens]
     with NativeConvServer(m, capacity_log2=21, elem_bits=bits, streams=4, max_batch_elems=1 << 19,
-                          solo_log2n=solo) as srv:
+                          solo_log2n=solo, host_arenas=host_arenas) as srv:
         tickets = []
         for f, g in reqs:
             bf, bg, t = srv.stage(f.size)
@@ -139,6 +142,36 @@ def test_native_server_admission_and_shutdown():
     with pytest.raises(nt.NttError) as e:
         srv.submit(np.zeros(1 << 15, np.uint32), np.zeros(1 << 15, np.uint32))    # larger than the arena
     assert e.value.name == "NTT_E_LENGTH"
+    srv.close()                                   # ten tickets still pending
+
+
+def test_native_server_host_arenas_submit_and_shutdown():
+    # host arenas of 2^14-word chunks: every submission takes a slot at once
+    # (new chunks as needed), results equal the requests run alone, a slot is
+    # reused after its result is read, tickets not waited for are released at
+    # shutdown
+    import paper_1005_1497_amd as nt
+    from paper_1005_1497_amd.serve import NativeConvServer
+    m = si.M_13631489
+    rng = np.random.default_rng(14)
+    reqs = [(rng.integers(0, m, 1 << int(n), dtype=np.uint32), rng.integers(0, m, 1 << int(n), dtype=np.uint32))
+            for n in rng.integers(4, 15, 60)]
+    srv = NativeConvServer(m, capacity_log2=14, elem_bits=32, streams=2, max_inflight=2, host_arenas=True)
+    tickets = [srv.submit(f, g) for f, g in reqs[:40]]
+    for (f, g), t in list(zip(reqs, tickets))[:30]:
+        assert np.array_equal(srv.result(t, timeout=60.0), host(nt.conv_circular(dev(f), dev(g), m)))
+    more = [srv.submit(f, g) for f, g in reqs[40:]]
+    for (f, g), t in zip(reqs[40:], more):
+        assert np.array_equal(srv.result(t, timeout=60.0), host(nt.conv_circular(dev(f), dev(g), m)))
+    with pytest.raises(nt.NttError) as e:
+        srv.submit(np.zeros(1 << 15, np.uint32), np.zeros(1 << 15, np.uint32))    # larger than a chunk
+    assert e.value.name == "NTT_E_LENGTH"
+    bf, bg, t = srv.stage(1 << 10)
+    f, g = rng.integers(0, m, 1 << 10, dtype=np.uint32), rng.integers(0, m, 1 << 10, dtype=np.uint32)
+    bf[...] = f
+    bg[...] = g
+    srv.submit_staged(t)
+    assert np.array_equal(srv.result(t, timeout=60.0), host(nt.conv_circular(dev(f), dev(g), m)))
     srv.close()                                   # ten tickets still pending
 
 
