@@ -210,6 +210,8 @@ def main():
                     help="serve, serve-sweep: the native scheduler's arenas: pinned host memory that the kernels read "
                          "and write directly (ntt_server_create_host), or device memory with copies each way "
                          "(ntt_server_create)")
+    ap.add_argument("--clients", type=int, default=2,
+                    help="serve-sweep: client thread pairs submitting to the native scheduler")
     ap.add_argument("--solo", type=int, default=16,
                     help="serve-sweep: requests of 2^SOLO words and more run as batches of their own (0: never)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -800,7 +802,7 @@ def serve_sweep(args):
     (20000 by default here) after 1000 warm-up ones, lengths 2^n with n uniform
     in [8, 18], m = 31065037602817 (64-bit words), Poisson arrivals at rho times
     the saturated throughput of the library's native scheduler (--arenas: host
-    arenas by default); beside each,
+    arenas by default; --clients submitting/waiting thread pairs, 2 by default); beside each,
     the same arrivals served one launch sequence per request (Python
     scheduler, one request per batch) where that form keeps up, and that form
     at rho times its own saturated throughput.  Every request has operands of
@@ -836,34 +838,48 @@ def serve_sweep(args):
             srv.result(t)
         srv.stats(reset=True)
         body = reqs[warm:]
-        gaps = np.random.default_rng(11).exponential(1.0 / rate, len(body)) if rate else np.zeros(len(body))
-        tickets = [None] * len(body)
-        ready = threading.Semaphore(0)
+        # --clients client pairs (a submitting and a waiting thread each) take
+        # every k-th request, each with Poisson gaps at rate / clients, so that
+        # the merged arrivals are Poisson at the rate; several clients keep one
+        # client's submission loop from capping the saturated throughput
+        k_cl = max(1, args.clients)
         gc.collect()
         gc.freeze()
         t_start = time.perf_counter()
 
-        def producer():
-            nxt = time.perf_counter()
-            for i, ((f, g), gap) in enumerate(zip(body, gaps)):
-                nxt += gap
-                d = nxt - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                tickets[i] = srv.submit(f, g)
-                ready.release()
+        def client(k):
+            part = body[k::k_cl]
+            gaps = (np.random.default_rng(11 + k).exponential(k_cl / rate, len(part)) if rate
+                    else np.zeros(len(part)))
+            tickets = [None] * len(part)
+            ready = threading.Semaphore(0)
+            sink = np.zeros(1 << 18, dtype=np.uint64)
 
-        sink = np.zeros(1 << 18, dtype=np.uint64)
+            def producer():
+                nxt = time.perf_counter()
+                for i, ((f, g), gap) in enumerate(zip(part, gaps)):
+                    nxt += gap
+                    d = nxt - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[i] = srv.submit(f, g)
+                    ready.release()
 
-        def consumer():
-            for i in range(len(body)):
-                ready.acquire()
-                srv.result(tickets[i], out=sink[:tickets[i][1]])
+            def consumer():
+                for i in range(len(part)):
+                    ready.acquire()
+                    srv.result(tickets[i], out=sink[:tickets[i][1]])
 
-        ths = [threading.Thread(target=producer), threading.Thread(target=consumer)]
-        for t in ths:
+            ths = [threading.Thread(target=producer), threading.Thread(target=consumer)]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+
+        cls = [threading.Thread(target=client, args=(k,)) for k in range(k_cl)]
+        for t in cls:
             t.start()
-        for t in ths:
+        for t in cls:
             t.join()
         el = time.perf_counter() - t_start
         st = srv.stats()
@@ -920,6 +936,7 @@ def serve_sweep(args):
                       "unit": "ms", "n_gpus": 1, "requests": n, "warmup": warm, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "serve_poisson_n2^8to2^18_m31065037602817", "words": "u64",
                                  "scheduler": "native (ntt_server_*), %s arenas" % args.arenas,
+                                 "clients": args.clients,
                                  "streams": args.streams,
                                  "max_inflight": args.inflight, "solo_log2n": args.solo,
                                  "max_batch_elems": 1 << (cap - 2)},
