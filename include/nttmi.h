@@ -178,7 +178,11 @@ ntt_status conv_circular_noalloc(uint64_t m, uint32_t log2n, uint64_t root, uint
  * and any tuning are then in place.  The captured kernels keep that stream's
  * workspace and work queue: replay the graph on that stream, or ordered with
  * every other use of it.  A workspace that a later call outgrows is retired,
- * not freed, so the graph stays valid until ntt_release_caches. */
+ * not freed, so the graph stays valid until ntt_release_caches.  f, g and h
+ * may be device memory or pinned host memory (hipHostMalloc, at the address
+ * the device sees): the kernels then load and store them over the host link,
+ * with no copies (ntt_server_create_host works so); the scratch stays on the
+ * device. */
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
                         const ntt_batch_desc *d, const void *f, const void *g, void *h,
                         uint32_t flags, void *stream);
