@@ -179,8 +179,9 @@ ntt_status conv_circular_noalloc(uint64_t m, uint32_t log2n, uint64_t root, uint
  * workspace and work queue: replay the graph on that stream, or ordered with
  * every other use of it.  A workspace that a later call outgrows is retired,
  * not freed, so the graph stays valid until ntt_release_caches.  f, g and h
- * may be device memory or pinned host memory (hipHostMalloc, at the address
- * the device sees): the kernels then load and store them over the host link,
+ * may be device memory or pinned host memory (hipHostMalloc, passed at the
+ * address hipHostGetDevicePointer gives): the kernels then load and store them
+ * over the host link,
  * with no copies (ntt_server_create_host works so); the scratch stays on the
  * device. */
 ntt_status conv_batched(uint64_t m, uint64_t root, uint32_t root_log2order, uint32_t elem_bits,
