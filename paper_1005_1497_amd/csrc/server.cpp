@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -146,6 +147,9 @@ struct ntt_server {
     // workgroup and every request of the batch completes with it; alone it
     // takes the four-step form spread over the chip.
     uint32_t solo_log2n = 16;
+    // how often the scheduler polls the events of batches in flight (tuning
+    // override: NTTMI_SERVER_POLL_US)
+    int poll_us = 10;
     size_t wb = 4;
     int dev = 0;
     bool host = false;                 // host arenas (ntt_server_create_host)
@@ -335,7 +339,7 @@ void ntt_server::run() {
         }
         // nothing launched or retired: sleep until a submission, or poll the
         // batches in flight again shortly
-        cv_sched.wait_for(lk, std::chrono::microseconds(inflight.empty() ? 2000 : 50));
+        cv_sched.wait_for(lk, std::chrono::microseconds(inflight.empty() ? 2000 : poll_us));
     }
 }
 
@@ -367,6 +371,10 @@ ntt_status create_server(uint64_t m, uint64_t root, uint32_t root_log2order, uin
     s->max_batch_elems = max_batch_elems ? max_batch_elems : (1ull << arena_log2);
     s->buddy = Buddy((int)arena_log2);
     s->host = host;
+    if (const char* pe = std::getenv("NTTMI_SERVER_POLL_US")) {
+        const int v = std::atoi(pe);
+        if (v > 0 && v <= 10000) s->poll_us = v;
+    }
     hipError_t e = hipGetDevice(&s->dev);
     const size_t bytes = (size_t(1) << arena_log2) * s->wb;
     if (e == hipSuccess && !host) e = hipMalloc((void**)&s->F, bytes);
