@@ -85,10 +85,10 @@ typedef enum {
                                         (ntt_max_log2n).  conv_batched:
                                         root_log2order <= v */
 #define NTT_FLAG_TRANSIENT     0x20u /* conv_batched: the descriptor is used once (a
-                                        served batch).  Its device copy goes through a
-                                        per-stream ring of staging slots, uploaded on
-                                        the stream, instead of the content-addressed
-                                        descriptor cache, so a stream of distinct
+                                        served batch).  It goes into a per-stream ring
+                                        of pinned host slots that the kernels read
+                                        directly (no copy), instead of the
+                                        content-addressed descriptor cache, so a stream of distinct
                                         batches never evicts that cache (which
                                         synchronises the device).  Ignored while the
                                         stream is being captured (captured kernels need
