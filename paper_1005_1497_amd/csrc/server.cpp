@@ -187,15 +187,19 @@ struct ntt_server {
 
     void run();
     bool launch(std::vector<Req*>& adm);
-    Chunk* host_slot(uint32_t log2n, uint64_t* off);
+    Chunk* host_slot(uint32_t log2n, uint64_t* off, std::unique_lock<std::mutex>& lk);
 };
 
 // Host arenas: a slot of 2^log2n words in the first chunk with room, else in a
-// new chunk; null when pinned memory runs out.  Called with mu held.
-Chunk* ntt_server::host_slot(uint32_t log2n, uint64_t* off) {
+// new chunk; null when pinned memory runs out.  Called with mu held through
+// `lk`, which it releases while it allocates a chunk (milliseconds), so that
+// the scheduler thread and the other clients do not wait for that; chunks are
+// kept until the server is destroyed.
+Chunk* ntt_server::host_slot(uint32_t log2n, uint64_t* off, std::unique_lock<std::mutex>& lk) {
     for (Chunk* c : chunks)
         if (c->buddy.alloc((int)log2n, off)) return c;
     const size_t bytes = (size_t(1) << arena_log2) * wb;
+    lk.unlock();
     Chunk* c = new Chunk();
     c->buddy = Buddy((int)arena_log2);
     hipError_t e = hipHostMalloc((void**)&c->F, bytes, hipHostMallocDefault);
@@ -208,8 +212,10 @@ Chunk* ntt_server::host_slot(uint32_t log2n, uint64_t* off) {
         for (char* p : {c->F, c->G, c->H})
             if (p) (void)hipHostFree(p);
         delete c;
+        lk.lock();
         return nullptr;
     }
+    lk.lock();
     chunks.push_back(c);
     return c;
 }
@@ -439,8 +445,8 @@ ntt_status ntt_server_submit(ntt_server* s, const void* f, const void* g, uint32
         r->state = Q_STAGED;
         char *fp = nullptr, *gp = nullptr;
         {
-            std::lock_guard<std::mutex> lk(s->mu);
-            Chunk* c = s->stop ? nullptr : s->host_slot(log2n, &r->off);
+            std::unique_lock<std::mutex> lk(s->mu);
+            Chunk* c = s->stop ? nullptr : s->host_slot(log2n, &r->off, lk);
             if (!c) {
                 const bool stopped = s->stop;
                 delete r;
@@ -497,8 +503,8 @@ ntt_status ntt_server_stage(ntt_server* s, uint32_t log2n, void** f, void** g, u
         Req* r = new Req();
         r->log2n = log2n;
         r->state = Q_STAGED;
-        std::lock_guard<std::mutex> lk(s->mu);
-        Chunk* c = s->stop ? nullptr : s->host_slot(log2n, &r->off);
+        std::unique_lock<std::mutex> lk(s->mu);
+        Chunk* c = s->stop ? nullptr : s->host_slot(log2n, &r->off, lk);
         if (!c) {
             const bool stopped = s->stop;
             delete r;
