@@ -204,13 +204,13 @@ def main():
                     help="lengths: the log2 N of the uniform 2^26-element batches")
     ap.add_argument("--rho", type=float, default=0.7, help="serve: offered load / saturated throughput")
     ap.add_argument("--rhos", default="0.3,0.5,0.7,0.9", help="serve-sweep: the offered loads")
-    ap.add_argument("--streams", type=int, default=4, help="serve-sweep: streams of the native scheduler")
-    ap.add_argument("--inflight", type=int, default=4, help="serve-sweep: batches in flight (native scheduler)")
+    ap.add_argument("--streams", type=int, default=8, help="serve-sweep: streams of the native scheduler")
+    ap.add_argument("--inflight", type=int, default=8, help="serve-sweep: batches in flight (native scheduler)")
     ap.add_argument("--arenas", choices=("host", "device"), default="host",
                     help="serve, serve-sweep: the native scheduler's arenas: pinned host memory that the kernels read "
                          "and write directly (ntt_server_create_host), or device memory with copies each way "
                          "(ntt_server_create)")
-    ap.add_argument("--clients", type=int, default=2,
+    ap.add_argument("--clients", type=int, default=4,
                     help="serve-sweep: client thread pairs submitting to the native scheduler")
     ap.add_argument("--solo", type=int, default=16,
                     help="serve-sweep: requests of 2^SOLO words and more run as batches of their own (0: never)")
@@ -802,7 +802,8 @@ def serve_sweep(args):
     (20000 by default here) after 1000 warm-up ones, lengths 2^n with n uniform
     in [8, 18], m = 31065037602817 (64-bit words), Poisson arrivals at rho times
     the saturated throughput of the library's native scheduler (--arenas: host
-    arenas by default; --clients submitting/waiting thread pairs, 2 by default); beside each,
+    arenas by default; --clients submitting/waiting thread pairs, 4 by default;
+    --streams and --inflight, 8 each by default); beside each,
     the same arrivals served one launch sequence per request (Python
     scheduler, one request per batch) where that form keeps up, and that form
     at rho times its own saturated throughput.  Every request has operands of
