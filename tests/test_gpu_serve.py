@@ -201,9 +201,11 @@ def test_native_server_zero_copy_submission():
         assert np.array_equal(o, host(nt.conv_circular(dev(f), dev(g), m)))
 
 
-def test_native_server_cross_thread_waits():
+@pytest.mark.parametrize("host_arenas", [False, True])
+def test_native_server_cross_thread_waits(host_arenas):
     # four submitting threads and four waiting threads, tickets handed over
     # through a queue: every result equals the same convolution run alone
+    # (host arenas: the submitters take slots, and new chunks, concurrently)
     import queue
     import threading
 
@@ -215,7 +217,8 @@ def test_native_server_cross_thread_waits():
             for n in rng.integers(4, 15, 240)]
     handoff = queue.Queue()
     results = {}
-    with NativeConvServer(m, capacity_log2=19, elem_bits=32, streams=3, max_batch=64) as srv:
+    with NativeConvServer(m, capacity_log2=19, elem_bits=32, streams=3, max_batch=64,
+                          host_arenas=host_arenas) as srv:
         def submitter(k):
             for i in range(k, len(reqs), 4):
                 handoff.put((i, srv.submit(*reqs[i])))
@@ -243,7 +246,8 @@ def test_native_server_cross_thread_waits():
         assert np.array_equal(results[i], host(nt.conv_circular(dev(f), dev(g), m))), i
 
 
-def test_native_server_one_waiter_per_ticket_and_timeout():
+@pytest.mark.parametrize("host_arenas", [False, True])
+def test_native_server_one_waiter_per_ticket_and_timeout(host_arenas):
     # two threads wait for the same ticket: one gets the result, the other
     # NTT_E_ARG (the ticket is taken, or already released); a wait whose time
     # runs out reports NTT_E_TIMEOUT and leaves the ticket valid
@@ -255,7 +259,7 @@ def test_native_server_one_waiter_per_ticket_and_timeout():
     rng = np.random.default_rng(15)
     f, g = (rng.integers(0, m, 1 << 18, dtype=np.uint32) for _ in range(2))
     want = host(nt.conv_circular(dev(f), dev(g), m))
-    with NativeConvServer(m, capacity_log2=19, elem_bits=32, streams=2) as srv:
+    with NativeConvServer(m, capacity_log2=19, elem_bits=32, streams=2, host_arenas=host_arenas) as srv:
         t = srv.submit(f, g)
         try:
             got = srv.result(t, timeout=0.0)
