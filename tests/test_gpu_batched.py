@@ -459,3 +459,37 @@ def test_descriptor_cache_eviction_keeps_descriptors_in_use(nt):
     ref = host(nt.conv_batched(f, g, desc, M, flags=nt.FLAG_PER_CLASS))
     assert np.array_equal(o, ref) and np.array_equal(o2, ref)
     _check_items(o, fh, gh, lengths, offs)
+
+
+def test_pinned_host_operands(nt):
+    # f, g and h in pinned host memory, passed at the addresses the device
+    # sees: the kernels load and store them over the host link, with no copies,
+    # and the result equals the batch on device operands (tiles, four-step and
+    # per-length forms, transient descriptors in pinned slots as well)
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")     # the runtime the process has loaded
+    lengths = [6, 9, 12, 13, 15, 16, 13, 8]
+    offs = si.offsets(lengths)
+    total = int(offs[-1]) + (1 << lengths[-1])
+    rng = np.random.default_rng(61)
+    fh = rng.integers(0, M, total, dtype=np.uint32)
+    gh = rng.integers(0, M, total, dtype=np.uint32)
+    desc = nt.BatchDesc(lengths, offs)
+    ref = host(nt.conv_batched(dev(fh), dev(gh), desc, M))
+    pf = torch.from_numpy(fh.view(np.int32)).pin_memory()
+    pg = torch.from_numpy(gh.view(np.int32)).pin_memory()
+    ph = torch.zeros(total, dtype=torch.int32).pin_memory()
+
+    def device_view(t):
+        p = ctypes.c_void_p()
+        assert hip.hipHostGetDevicePointer(ctypes.byref(p), ctypes.c_void_p(t.data_ptr()), 0) == 0
+        return p
+
+    for flags in (0, nt.FLAG_TRANSIENT):
+        ph.zero_()
+        st = nt.lib.conv_batched(M, 2, 19, 32, ctypes.byref(desc.c), device_view(pf), device_view(pg),
+                                 device_view(ph), flags, None)
+        assert st == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(ph.numpy().view(np.uint32), ref), flags
+    _check_items(ph.numpy().view(np.uint32), fh, gh, lengths, offs)
