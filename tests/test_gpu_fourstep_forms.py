@@ -70,30 +70,34 @@ def test_ntt_rows_with_row_loops(nt):
     assert np.array_equal(y, x)
 
 
-@pytest.mark.parametrize("n,count", [(13, 200), (14, 100), (15, 100), (16, 100)])
-def test_fourstep_workgroup_sizes_agree(nt, n, count):
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("n,count", [(13, 150), (14, 100), (15, 100), (16, 100)])
+def test_fourstep_workgroup_sizes_agree(nt, n, count, bits):
     # count is large enough that the batch's 512-thread column blocks give
     # every CU one, and below two thirds of the fused kernel's residency, so
     # the batch runs the 512-thread four-step kernels; each item alone
     # (FLAG_PER_ITEM) runs the 256-thread ones
+    import seeded_inputs as si
+    m = M if bits == 32 else si.M_U64
+    dt = np.uint32 if bits == 32 else np.uint64
     N = 1 << n
-    rng = np.random.default_rng(200 + n)
-    f = rng.integers(0, M, count * N, dtype=np.uint32)
-    g = rng.integers(0, M, count * N, dtype=np.uint32)
-    f[:N] = M - 1                      # item 0 at the top of the canonical range
+    rng = np.random.default_rng(200 + n + bits)
+    f = rng.integers(0, m, count * N, dtype=dt)
+    g = rng.integers(0, m, count * N, dtype=dt)
+    f[:N] = m - 1                      # item 0 at the top of the canonical range
     desc = nt.BatchDesc([n] * count, [i * N for i in range(count)])
     before = nt.launch_counts()
-    h = host(nt.conv_batched(dev(f), dev(g), desc, M))
+    h = host(nt.conv_batched(dev(f), dev(g), desc, m))
     assert _delta(nt, before)["fourstep"] == 1
-    h1 = host(nt.conv_batched(dev(f), dev(g), desc, M, flags=nt.FLAG_PER_ITEM))
+    h1 = host(nt.conv_batched(dev(f), dev(g), desc, m, flags=nt.FLAG_PER_ITEM))
     assert np.array_equal(h, h1)
     for i in (0, count - 1):
         idx = np.unique(np.concatenate([[0, 1, N // 2, N - 1], rng.integers(0, N, 12)])).astype(np.uint64)
-        ref = oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], M, idx)
-        assert np.array_equal(h[i * N + idx.astype(np.int64)], ref.astype(np.uint32)), i
+        ref = oracle.conv_entries(f[i * N:(i + 1) * N], g[i * N:(i + 1) * N], m, idx)
+        assert np.array_equal(h[i * N + idx.astype(np.int64)], ref.astype(dt)), i
     # transforms: 64 rows (512-thread blocks from 2^15 on) against one row
-    x = rng.integers(0, M, (64, N), dtype=np.uint32)
-    X = host(nt.ntt_forward(dev(x), M))
-    X0 = host(nt.ntt_forward(dev(x[:1]), M))
+    x = rng.integers(0, m, (64, N), dtype=dt)
+    X = host(nt.ntt_forward(dev(x), m))
+    X0 = host(nt.ntt_forward(dev(x[:1]), m))
     assert np.array_equal(X[:1], X0)
-    assert np.array_equal(host(nt.ntt_inverse(dev(X0), M)), x[:1])
+    assert np.array_equal(host(nt.ntt_inverse(dev(X0), m)), x[:1])
